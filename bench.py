@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of the D2Q9 KBC stream-and-collide step on one MI355X.
+
+Workload (the roofline run): one periodic 16384 x 16384 lattice, a seeded
+divergence-free random initial field with E(k) ~ k^4 exp(-2 (k/32)^2),
+u_rms = 0.05, rho = 1, nu = 1e-4, Grad initialisation with central
+differences; KBC model B, populations stored as FP32 deviations, FP32
+arithmetic.  One step is one fused pull-stream + collide launch over the
+whole lattice.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+prints one JSON line.  `value` is lattice updates per second (MLUPS) over the
+K timed steps; `roofline` relates the kernel's algorithmic bytes (9 loads + 9
+stores of 4 bytes per node) to the MI355X HBM peak; `cpu_baseline` times the
+FP64 CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % of HBM roofline (KBC fwd, adjoint) at stated error vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = {"f16": 36, "f32": 72, "f64": 144}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
+STEP_SOURCES = [os.path.join(ROOT, "paper_1507_02509_amd", "csrc", f)
+                for f in ("kbc_step.hip", "kbc_device.hpp")]
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for p in STEP_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_digest") != kernel_digest():
+        return None
+    entry = rec.get("workloads", {}).get(key)
+    return None if entry is None else entry.get("bytes_per_launch")
+
+
+def time_steps(sim, steps: int, warmup: int):
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    return t0.elapsed_time(t1) / steps, wall
+
+
+def make_sim(n, form, collision, variant, nu, seed, k0, device):
+    from paper_1507_02509_amd import inputs
+    from paper_1507_02509_amd.sim import Sim, beta_from_nu
+    ux, uy = inputs.spectral(n, k0, 0.05, seed=seed, device=device)
+    sim = Sim(n, n, beta_from_nu(nu), collision=collision, variant=variant, form=form, device=device)
+    sim.init(ux, uy)
+    del ux, uy
+    return sim
+
+
+def cpu_baseline(n: int, nu: float, seed: int, k0: float, target_s: float = 12.0):
+    """The FP64 oracle (unmodified) on a 2048-row slab of the same workload,
+    treated as a periodic 16384 x 2048 lattice (the same per-node work)."""
+    import oracle
+    from paper_1507_02509_amd import inputs
+    rows = 2048
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    threads = max(1, min(threads, 16))
+    ux, uy = inputs.spectral(n, k0, 0.05, seed=seed, device="cuda")
+    ux = np.ascontiguousarray(ux[:rows].cpu().numpy())
+    uy = np.ascontiguousarray(uy[:rows].cpu().numpy())
+    p = oracle.Params(n, rows, 1.0 / (6.0 * nu + 1.0), collision=oracle.KBC, variant=oracle.KBC_B,
+                      threads=threads)
+    f = oracle.init(p, ux, uy)
+    t0 = time.perf_counter()
+    f1 = oracle.step(p, f)
+    one = time.perf_counter() - t0
+    nsteps = max(1, int(target_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        f1 = oracle.step(p, f1)
+    dt = time.perf_counter() - t0
+    total = nsteps + 1
+    mlups = n * rows * total / (dt + one) / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"KBC-B FP64 oracle, {total} steps of a periodic {n} x {rows} slab of the "
+                      f"same seeded field ({n * rows * total / 1e6:.0f} M node updates, {dt + one:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--form", default="f32", choices=["f16", "f32", "f64"])
+    ap.add_argument("--variant", default="B")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    dev = "cuda:0"
+    n, nu, seed, k0 = args.n, 1e-4, 3, 32
+    workload = f"d2q9_kbc{args.variant}_turbulence_{n}x{n}_k0_{k0}_nu_1e-4"
+
+    sim = make_sim(n, args.form, "kbc", args.variant, nu, seed, k0, dev)
+    ms, wall = time_steps(sim, args.steps, args.warmup)
+    d = sim.diagnostics()
+    del sim
+    torch.cuda.empty_cache()
+    nodes = n * n
+    mlups = nodes / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_NODE[args.form] * nodes / (ms * 1e-3) / 1e9
+    key = f"{args.form}_kbc{args.variant}_{n}"
+    traffic = measured_traffic(key)
+
+    extras = {}
+    if not args.no_extras:
+        # the same workload in the other storage forms and with the LBGK baseline
+        for form in ("f16", "f64"):
+            if form == args.form:
+                continue
+            s = make_sim(n, form, "kbc", args.variant, nu, seed, k0, dev)
+            m, _ = time_steps(s, 50, 5)
+            del s
+            torch.cuda.empty_cache()
+            extras[f"kbc{args.variant}_{form}"] = {
+                "mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4),
+                "hbm_frac": round(BYTES_PER_NODE[form] * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        s = make_sim(n, args.form, "lbgk", "A", nu, seed, k0, dev)
+        m, _ = time_steps(s, 50, 5)
+        del s
+        torch.cuda.empty_cache()
+        extras[f"lbgk_{args.form}"] = {"mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4)}
+        extras["kbc_over_lbgk_time"] = round(ms / m, 3)
+        # the copy reference: 2 x 1.2 GB read + write
+        from paper_1507_02509_amd.sim import copy_probe
+        a = torch.empty(300_000_000, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        copy_probe(b, a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            copy_probe(b, a)
+        e1.record()
+        torch.cuda.synchronize()
+        cms = e0.elapsed_time(e1) / 10
+        extras["copy_probe_GBs"] = round(2 * a.numel() * 4 / (cms * 1e-3) / 1e9, 1)
+        del a, b
+        torch.cuda.empty_cache()
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f16": "f32 (f16 storage)", "f32": "f32", "f64": "f64"}[args.form],
+        "data": "synthetic",
+        "config": {"workload": workload, "nx": n, "ny": n, "collision": f"KBC-{args.variant}",
+                   "form": f"{args.form}dev" if args.form != "f64" else "f64", "nu": nu, "seed": seed,
+                   "k0": k0, "u_rms": 0.05, "init": "grad_cd"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": f"k_step<{args.form},KBC-{args.variant}>",
+                     "algorithmic_bytes_per_launch": BYTES_PER_NODE[args.form] * nodes},
+        "wall_s_timed": round(wall, 3),
+        "final_state": {"mass_drift_rel": None, "E": d["E"], "Z": d["Z"], "gamma_mean": d["gamma"],
+                        "n_nonfinite": d["n_nonfinite"]},
+        "extras": extras,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, nu, seed, k0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

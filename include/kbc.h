@@ -1,0 +1,177 @@
+/*
+ * kbc.h -- C ABI of libkbc, the MI355X (gfx950) implementation of the D2Q9
+ * lattice Boltzmann stream-and-collide step with the entropic multi-relaxation
+ * (KBC) collision of Boesch, Chikatamarla and Karlin, "Entropic
+ * Multi-Relaxation Models for Simulation of Fluid Turbulence"
+ * (arXiv:1507.02509), and the LBGK baseline.
+ *
+ * Model (paper sections cited per entry point):
+ *   f_i(x + v_i, t + 1) = f_i' = (1 - beta) f_i(x, t) + beta f_i^mirr(x, t)
+ *                                                               eq. (Egeneral)
+ *   LBGK: f^mirr = 2 feq - f                                    eq. (LBGKmirr)
+ *   KBC:  f^mirr = k + [2 s^eq - s] + [gamma h^eq + (1 - gamma) h]
+ *                                                            eq. (ksh-mirror)
+ *         with the moment groups of Table kbc_moment_grouping and
+ *         gamma = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh>      eq. (result21)
+ *   feq: second-order polynomial equilibrium                       eq. (Eq)
+ *   nu = cs2 (1/(2 beta) - 1/2), cs2 = 1/3                   eq. (viscosity)
+ *
+ * Lattice conventions:
+ *   velocity order i = 0..8: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
+ *   (-1,-1) (1,-1); weights W = 4/9, 1/9 (x4), 1/36 (x4); periodic in x and y.
+ *
+ * Storage (device memory owned by the caller, e.g. torch tensors):
+ *   a population buffer is 9 planes of ny rows of `pitch` elements, element
+ *   (i, y, x) at offset (i * ny + y) * pitch + x, x fastest.  The stored value
+ *   is the deviation g_i = f_i - W_i rho0 in the form's storage type:
+ *     LBM_F16DEV_F32: binary16 holding g_i * 2^s_i (s = 1 for i = 0, 3 for the
+ *                     axis velocities, 5 for the diagonals), FP32 arithmetic;
+ *     LBM_F32DEV_F32: binary32 g_i, FP32 arithmetic;
+ *     LBM_F64:        binary64 g_i, FP64 arithmetic.
+ *   The step is a fused pull: each node gathers buf_i(x - v_i), collides and
+ *   writes buf'_i(x).  Hence the buffer after n steps holds the post-collision
+ *   state of step n-1 at its source node, and the pre-collision state the
+ *   paper calls f(x, t = n) is f_i(x) = buf_i(x - v_i) + W_i rho0.  Every entry
+ *   point that reads or writes "the state" uses f(x, t = n) in that sense.
+ *
+ * Macroscopic fields (rho, u_x, u_y, gamma, gradients) are dense FP64 device
+ * arrays [ny][nx], x fastest.
+ *
+ * Calls are stream-ordered on params.stream (a hipStream_t; NULL = the null
+ * stream) and return LBM_OK (0) or a negative LBM_E* code; lbm_last_error()
+ * then holds a message for the calling thread.  Argument checks run before
+ * any HIP call.  No entry point synchronises the stream unless it says so.
+ */
+#ifndef KBC_H
+#define KBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,        /* invalid argument */
+    LBM_EHIP = -2,          /* a HIP runtime call failed */
+    LBM_ENOMEM = -3,        /* device or host allocation failed */
+    LBM_ENONFINITE = -4,    /* reserved for callers that check diagnostics */
+    LBM_EUNSUPPORTED = -5   /* valid but not implemented combination */
+};
+
+/* collision: LBGK eq. (LBGKmirr) or KBC eq. (ksh-mirror) */
+typedef enum { LBM_LBGK = 0, LBM_KBC = 1 } lbm_collision;
+/* moment grouping of Table kbc_moment_grouping */
+typedef enum { LBM_KBC_A = 0, LBM_KBC_B = 1, LBM_KBC_C = 2, LBM_KBC_D = 3 } lbm_variant;
+/* storage / arithmetic form (see "Storage" above) */
+typedef enum { LBM_F16DEV_F32 = 0, LBM_F32DEV_F32 = 1, LBM_F64 = 2 } lbm_form;
+/* stabiliser: gamma* of eq. (result21) with the denominator guard, a fixed
+ * value (gamma_fixed; 2 gives LBGK, 1/beta the regularised model), or the
+ * root of eq. (result1) by Newton iteration from gamma* */
+typedef enum { LBM_GAMMA_ESTIMATE = 0, LBM_GAMMA_FIXED = 1, LBM_GAMMA_EXACT = 2 } lbm_gamma_mode;
+/* initial populations: equilibrium eq. (Eq); Grad's approximation eq. (Grad)
+ * with Pi = Pi^eq + Pi^(1) (eqs. Peq, P1AC) and velocity gradients from
+ * second-order central differences, or from the caller */
+typedef enum { LBM_INIT_EQ = 0, LBM_INIT_GRAD_CD = 1, LBM_INIT_GRAD_GIVEN = 2 } lbm_init_mode;
+
+typedef struct {
+    int32_t nx, ny;        /* lattice size, each >= 3 */
+    double beta;           /* relaxation parameter, 0 < beta <= 1 */
+    double rho0;           /* reference density of the deviation storage (> 0, usually 1) */
+    int32_t collision;     /* lbm_collision */
+    int32_t variant;       /* lbm_variant (ignored for LBGK) */
+    int32_t form;          /* lbm_form */
+    int32_t gamma_mode;    /* lbm_gamma_mode */
+    double gamma_guard;    /* gamma = 2 where <dh|dh> <= gamma_guard * <ds|ds> (>= 0; default 1e-12) */
+    double gamma_fixed;    /* stabiliser for LBM_GAMMA_FIXED */
+    void* stream;          /* hipStream_t all work is ordered on */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Diagnostics of the state f(x, t = n) (section "Decaying Two-Dimensional
+ * Turbulence" statistics): totals, spatial means and standard deviations of
+ * e = |u|^2/2, z = omega^2/2 and p = |grad omega|^2/2 (omega and its gradient
+ * by second-order central differences), mean entropy per node eq. (S), mean
+ * and standard deviation of gamma, node counts with a non-finite population or
+ * a non-positive equilibrium population.  Sums are accumulated in FP64. */
+typedef struct {
+    double mass, jx, jy;
+    double E, E_std, Z, Z_std, P, P_std;
+    double S, gamma, gamma_std;
+    double n_nonfinite, n_feq_nonpos;
+    double rho_std;
+    double reserved;
+} lbm_diag;
+
+/* Smallest legal pitch (elements) for nx in form f: nx rounded up to 64.
+ * Returns 0 for invalid arguments. */
+size_t lbm_required_pitch(int32_t nx, int32_t form);
+
+/* Bytes of one population buffer: 9 * ny * pitch * sizeof(storage type). */
+size_t lbm_buffer_bytes(int32_t nx, int32_t ny, int32_t form);
+
+/* Create a context over two caller-owned population buffers (buf_a, buf_b,
+ * each lbm_buffer_bytes; they must not overlap; pitch_elems >= the required
+ * pitch and a multiple of 64) and write the initial state into buf_a, per
+ * `mode` from rho (NULL: uniform rho0), ux, uy and, for LBM_INIT_GRAD_GIVEN,
+ * grad[4][ny][nx] = (d_x u_x, d_y u_x, d_x u_y, d_y u_y) (section
+ * "Green-Taylor Vortex Flow", eq. (Grad); central differences as in the
+ * turbulence section).  The macroscopic inputs are read before the call's
+ * work completes on the stream; keep them alive until then.  *out receives
+ * the context; the caller frees it with lbm_free. */
+int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_t pitch_elems,
+             const double* rho, const double* ux, const double* uy, const double* grad,
+             int32_t mode);
+
+/* Advance nsteps >= 0 time steps of eq. (Egeneral): one fused pull-stream +
+ * collide launch per step, alternating the two buffers.  Enqueues only; does
+ * no value checks (see lbm_diagnostics). */
+int lbm_step(lbm_ctx* c, int32_t nsteps);
+
+/* Density, velocity and (optionally) the stabiliser gamma the next collision
+ * would use, of f(x, t = n).  Each output is a dense FP64 device array
+ * [ny][nx] or NULL. */
+int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* gamma);
+
+/* Export / import f(x, t = n) as full FP64 populations [9][ny][nx] (device). */
+int lbm_get_populations(lbm_ctx* c, double* f);
+int lbm_set_populations(lbm_ctx* c, const double* f);
+
+/* Diagnostics of f(x, t = n) into *out (host).  Synchronises the stream. */
+int lbm_diagnostics(lbm_ctx* c, lbm_diag* out);
+
+/* Steps taken since lbm_init (or the last lbm_set_step). */
+int64_t lbm_step_count(const lbm_ctx* c);
+int lbm_set_step(lbm_ctx* c, int64_t n);
+
+/* Device pointer of the buffer holding the current state and of the other one. */
+void* lbm_state_buffer(const lbm_ctx* c);
+void* lbm_work_buffer(const lbm_ctx* c);
+
+/* Workgroup tile of the step kernel: 64 x `rows` nodes, rows in {4, 8, 16}
+ * (default 4).  A tuning knob only: results are bitwise identical for every
+ * tile. */
+int lbm_set_tile(lbm_ctx* c, int32_t rows);
+
+/* Replace beta (e.g. between rollouts); other parameters are fixed per ctx. */
+int lbm_set_beta(lbm_ctx* c, double beta);
+
+/* Release the context and the scratch memory it allocated (never the
+ * caller's buffers).  Synchronises the stream.  NULL is accepted. */
+int lbm_free(lbm_ctx* c);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+/* Streaming copy dst[i] = src[i] of n 4-byte words on `stream`: the bandwidth
+ * reference measured beside the step. */
+int lbm_copy_probe(void* dst, const void* src, size_t n_words, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,279 @@
+// kbc_capi.hip -- the C ABI declared in include/kbc.h.
+//
+// A context borrows the caller's two population buffers and records the
+// lattice parameters, the step counter and the buffer that holds the current
+// state.  Its only allocations are the scratch arrays of lbm_diagnostics.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "kbc.h"
+#include "kbc_launch.hpp"
+
+struct lbm_ctx {
+    lbm_params p;
+    kbc::Lattice L;
+    void* buf[2];
+    int cur;                // index of the buffer holding the current state
+    int64_t steps;
+    kbc::StepShape shape;
+    double* dscratch;       // ux, uy, omega fields + diagnostics partials
+    size_t dscratch_elems;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int launch_result(int rc, const char* what) {
+    if (rc == 0) return LBM_OK;
+    if (rc == -1) return fail(LBM_EINVAL, "%s: invalid configuration", what);
+    if (rc == -5) return fail(LBM_EUNSUPPORTED, "%s: combination not built", what);
+    return fail(LBM_EHIP, "%s: kernel launch failed: %s", what, hipGetErrorString(hipGetLastError()));
+}
+
+size_t form_bytes(int32_t form) {
+    switch (form) {
+        case LBM_F16DEV_F32: return 2;
+        case LBM_F32DEV_F32: return 4;
+        case LBM_F64: return 8;
+        default: return 0;
+    }
+}
+
+int check_params(const lbm_params* p) {
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail(LBM_EINVAL, "nx, ny must be >= 3 (got %d x %d)", p->nx, p->ny);
+    if (!(p->beta > 0.0 && p->beta <= 1.0)) return fail(LBM_EINVAL, "beta must be in (0, 1] (got %g)", p->beta);
+    if (!(p->rho0 > 0.0) || !isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
+    if (p->collision != LBM_LBGK && p->collision != LBM_KBC) return fail(LBM_EINVAL, "unknown collision %d", p->collision);
+    if (p->variant < LBM_KBC_A || p->variant > LBM_KBC_D) return fail(LBM_EINVAL, "unknown variant %d", p->variant);
+    if (form_bytes(p->form) == 0) return fail(LBM_EINVAL, "unknown form %d", p->form);
+    if (p->gamma_mode < LBM_GAMMA_ESTIMATE || p->gamma_mode > LBM_GAMMA_EXACT)
+        return fail(LBM_EINVAL, "unknown gamma_mode %d", p->gamma_mode);
+    if (!(p->gamma_guard >= 0.0) || !isfinite(p->gamma_guard)) return fail(LBM_EINVAL, "gamma_guard must be finite and >= 0");
+    if (p->gamma_mode == LBM_GAMMA_FIXED && !isfinite(p->gamma_fixed)) return fail(LBM_EINVAL, "gamma_fixed must be finite");
+    if (p->collision == LBM_KBC && p->gamma_mode == LBM_GAMMA_EXACT)
+        return fail(LBM_EUNSUPPORTED, "LBM_GAMMA_EXACT is not built in this library");
+    return LBM_OK;
+}
+
+kbc::Lattice lattice_of(const lbm_params& p, size_t pitch) {
+    kbc::Lattice L;
+    L.nx = p.nx;
+    L.ny = p.ny;
+    L.pitch = static_cast<int64_t>(pitch);
+    L.form = p.form;
+    L.collision = p.collision;
+    L.variant = p.variant;
+    L.gamma_mode = p.gamma_mode;
+    L.beta = p.beta;
+    L.rho0 = p.rho0;
+    L.guard = p.gamma_guard;
+    L.gamma_fixed = p.gamma_fixed;
+    L.stream = static_cast<hipStream_t>(p.stream);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err; }
+
+size_t lbm_required_pitch(int32_t nx, int32_t form) {
+    if (nx < 1 || form_bytes(form) == 0) return 0;
+    return (static_cast<size_t>(nx) + 63) / 64 * 64;
+}
+
+size_t lbm_buffer_bytes(int32_t nx, int32_t ny, int32_t form) {
+    const size_t pitch = lbm_required_pitch(nx, form);
+    if (pitch == 0 || ny < 1) return 0;
+    return 9 * static_cast<size_t>(ny) * pitch * form_bytes(form);
+}
+
+int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_t pitch_elems,
+             const double* rho, const double* ux, const double* uy, const double* grad, int32_t mode) {
+    g_err[0] = 0;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!buf_a || !buf_b) return fail(LBM_EINVAL, "population buffers must not be NULL");
+    const size_t need = lbm_required_pitch(p->nx, p->form);
+    if (pitch_elems < need || pitch_elems % 64 != 0)
+        return fail(LBM_EINVAL, "pitch %zu must be >= %zu and a multiple of 64", pitch_elems, need);
+    const size_t bytes = 9 * static_cast<size_t>(p->ny) * pitch_elems * form_bytes(p->form);
+    const char* a = static_cast<const char*>(buf_a);
+    const char* b = static_cast<const char*>(buf_b);
+    if (a < b + bytes && b < a + bytes) return fail(LBM_EINVAL, "population buffers overlap");
+    if (mode < LBM_INIT_EQ || mode > LBM_INIT_GRAD_GIVEN) return fail(LBM_EINVAL, "unknown init mode %d", mode);
+    if (!ux || !uy) return fail(LBM_EINVAL, "ux and uy must not be NULL");
+    if (mode == LBM_INIT_GRAD_GIVEN && !grad) return fail(LBM_EINVAL, "LBM_INIT_GRAD_GIVEN needs grad");
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_ENOMEM, "context allocation failed");
+    c->p = *p;
+    c->L = lattice_of(*p, pitch_elems);
+    c->buf[0] = buf_a;
+    c->buf[1] = buf_b;
+    c->cur = 0;
+    c->steps = 0;
+    c->shape.rows = 4;
+    c->dscratch = nullptr;
+    c->dscratch_elems = 0;
+    rc = kbc::launch_init(c->L, buf_a, rho, ux, uy, grad, mode);
+    if (rc) {
+        delete c;
+        return launch_result(rc, "lbm_init");
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int32_t nsteps) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    for (int32_t s = 0; s < nsteps; ++s) {
+        const int rc = kbc::launch_step(c->L, c->buf[c->cur], c->buf[c->cur ^ 1], c->shape);
+        if (rc) return launch_result(rc, "lbm_step");
+        c->cur ^= 1;
+        ++c->steps;
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* gamma) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!rho && !ux && !uy && !gamma) return LBM_OK;
+    return launch_result(kbc::launch_moments(c->L, c->buf[c->cur], rho, ux, uy, gamma), "lbm_moments");
+}
+
+int lbm_get_populations(lbm_ctx* c, double* f) {
+    if (!c || !f) return fail(LBM_EINVAL, "ctx and f must not be NULL");
+    return launch_result(kbc::launch_get_pop(c->L, c->buf[c->cur], f), "lbm_get_populations");
+}
+
+int lbm_set_populations(lbm_ctx* c, const double* f) {
+    if (!c || !f) return fail(LBM_EINVAL, "ctx and f must not be NULL");
+    return launch_result(kbc::launch_set_pop(c->L, c->buf[c->cur], f), "lbm_set_populations");
+}
+
+int lbm_diagnostics(lbm_ctx* c, lbm_diag* out) {
+    if (!c || !out) return fail(LBM_EINVAL, "ctx and out must not be NULL");
+    const size_t N = static_cast<size_t>(c->p.nx) * c->p.ny;
+    const size_t need = 3 * N + static_cast<size_t>(kbc::kDiagBlocks) * kbc::kDiagSlots;
+    if (c->dscratch_elems < need) {
+        if (c->dscratch) {
+            hipError_t e = hipStreamSynchronize(c->L.stream);
+            if (e != hipSuccess) return hip_fail(e, "lbm_diagnostics sync");
+            (void)hipFree(c->dscratch);
+            c->dscratch = nullptr;
+            c->dscratch_elems = 0;
+        }
+        hipError_t e = hipMalloc(&c->dscratch, need * sizeof(double));
+        if (e != hipSuccess) {
+            c->dscratch = nullptr;
+            return fail(LBM_ENOMEM, "diagnostics scratch: %s", hipGetErrorString(e));
+        }
+        c->dscratch_elems = need;
+    }
+    double* ux_s = c->dscratch;
+    double* uy_s = ux_s + N;
+    double* w_s = uy_s + N;
+    double* part = w_s + N;
+    int rc = kbc::launch_diag(c->L, c->buf[c->cur], ux_s, uy_s, w_s, part);
+    if (rc) return launch_result(rc, "lbm_diagnostics");
+    std::vector<double> h(static_cast<size_t>(kbc::kDiagBlocks) * kbc::kDiagSlots);
+    hipError_t e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->L.stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_diagnostics copy");
+    e = hipStreamSynchronize(c->L.stream);
+    if (e != hipSuccess) return hip_fail(e, "lbm_diagnostics sync");
+    double s[kbc::kDiagSlots] = {0};
+    for (int b = 0; b < kbc::kDiagBlocks; ++b)
+        for (int k = 0; k < kbc::kDiagSlots; ++k) s[k] += h[static_cast<size_t>(b) * kbc::kDiagSlots + k];
+    const double n = static_cast<double>(N);
+    auto sd = [n](double sum, double sum2) {
+        const double m = sum / n;
+        const double v = sum2 / n - m * m;
+        return v > 0.0 ? sqrt(v) : 0.0;
+    };
+    out->mass = s[0];
+    out->jx = s[1];
+    out->jy = s[2];
+    out->E = s[3] / n;
+    out->E_std = sd(s[3], s[4]);
+    out->S = s[5] / n;
+    out->gamma = s[6] / n;
+    out->gamma_std = sd(s[6], s[7]);
+    out->n_nonfinite = s[8];
+    out->n_feq_nonpos = s[9];
+    out->rho_std = sd(s[0], s[10]);
+    out->Z = s[11] / n;
+    out->Z_std = sd(s[11], s[12]);
+    out->P = s[13] / n;
+    out->P_std = sd(s[13], s[14]);
+    out->reserved = 0.0;
+    return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+int lbm_set_step(lbm_ctx* c, int64_t n) {
+    if (!c || n < 0) return fail(LBM_EINVAL, "invalid ctx or step");
+    c->steps = n;
+    return LBM_OK;
+}
+
+void* lbm_state_buffer(const lbm_ctx* c) { return c ? c->buf[c->cur] : nullptr; }
+void* lbm_work_buffer(const lbm_ctx* c) { return c ? c->buf[c->cur ^ 1] : nullptr; }
+
+int lbm_set_tile(lbm_ctx* c, int32_t rows) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (rows != 4 && rows != 8 && rows != 16) return fail(LBM_EINVAL, "tile rows must be 4, 8 or 16");
+    c->shape.rows = rows;
+    return LBM_OK;
+}
+
+int lbm_set_beta(lbm_ctx* c, double beta) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(LBM_EINVAL, "beta must be in (0, 1]");
+    c->p.beta = beta;
+    c->L.beta = beta;
+    return LBM_OK;
+}
+
+int lbm_free(lbm_ctx* c) {
+    if (!c) return LBM_OK;
+    int rc = LBM_OK;
+    if (c->dscratch) {
+        hipError_t e = hipStreamSynchronize(c->L.stream);
+        if (e != hipSuccess) rc = hip_fail(e, "lbm_free sync");
+        (void)hipFree(c->dscratch);
+    }
+    delete c;
+    return rc;
+}
+
+int lbm_copy_probe(void* dst, const void* src, size_t n_words, void* stream) {
+    if (!dst || !src) return fail(LBM_EINVAL, "dst and src must not be NULL");
+    return launch_result(kbc::launch_copy(dst, src, n_words, static_cast<hipStream_t>(stream)), "lbm_copy_probe");
+}
+
+}  // extern "C"

@@ -1,0 +1,214 @@
+// kbc_device.hpp -- per-node arithmetic of the D2Q9 KBC / LBGK step for gfx950.
+//
+// The collision works on deviations g_i = f_i - W_i rho0 (the stored form) and
+// never forms full populations.  Everything it needs follows from six
+// non-equilibrium moments of df = f - feq, which are cheap in deviation form
+// because the second-order polynomial equilibrium (eq. Eq) has closed-form
+// moments on D2Q9: rho, rho u, Pi^eq = rho cs2 I + rho u u (eq. Peq),
+// Q^eq_xyy = rho u_x / 3, Q^eq_yxx = rho u_y / 3 (eq. Qeq) and
+// A^eq = rho / 9 + rho |u|^2 / 3.  With T = P_xx + P_yy, N = P_xx - P_yy,
+// Pi = P_xy (eq. natmoments1), the shear part ds and the higher-order part dh
+// of Table kbc_moment_grouping are populations of a moment vector
+// (T, N, Pi, Q_xyy, Q_yxx, A) through eq. (momentsD2Q9); for the central-moment
+// models A and B the shear moments are carried to natural ones by the linear
+// part of eq. (cm) (at fixed u the central deviations equal the natural ones).
+// gamma follows eq. (result21) with the entropic scalar product weighted by
+// 1/feq; the common factor 1/rho cancels in the ratio and in the guard.
+//
+// All floating-point contractions are written out with fma() and the library
+// is compiled with -ffp-contract=off, so every launch shape that runs this
+// code produces bitwise identical results.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kbc {
+
+enum Coll { LBGK = 0, KBCC = 1 };
+enum Var { VA = 0, VB = 1, VC = 2, VD = 3 };
+enum GMode { GEST = 0, GFIX = 1, GEXACT = 2 };
+enum FormId { F16 = 0, F32 = 1, F64 = 2 };
+
+// D2Q9 velocities, order (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
+constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+// lattice weights 4/9, 1/9, 1/36 and their inverses
+__host__ __device__ constexpr double weight(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+__host__ __device__ constexpr double inv_weight(int i) { return i == 0 ? 2.25 : (i < 5 ? 9.0 : 36.0); }
+// binary16 storage scale exponents: ~1/W_i rounded to a power of two
+__host__ __device__ constexpr int f16_shift(int i) { return i == 0 ? 1 : (i < 5 ? 3 : 5); }
+
+// ---------------------------------------------------------------- storage forms
+template <int FORM> struct Form;
+
+template <> struct Form<F16> {
+    using S = _Float16;
+    using R = float;
+    static constexpr int bytes = 2;
+    __device__ static __forceinline__ R dec(S v, int i) {
+        return static_cast<float>(v) * (1.0f / static_cast<float>(1 << f16_shift(i)));
+    }
+    __device__ static __forceinline__ S enc(R v, int i) {
+        return static_cast<_Float16>(v * static_cast<float>(1 << f16_shift(i)));
+    }
+    __device__ static __forceinline__ double dec64(S v, int i) {
+        return static_cast<double>(static_cast<float>(v)) / static_cast<double>(1 << f16_shift(i));
+    }
+    __device__ static __forceinline__ S enc64(double v, int i) {
+        return static_cast<_Float16>(static_cast<float>(v * static_cast<double>(1 << f16_shift(i))));
+    }
+};
+
+template <> struct Form<F32> {
+    using S = float;
+    using R = float;
+    static constexpr int bytes = 4;
+    __device__ static __forceinline__ R dec(S v, int) { return v; }
+    __device__ static __forceinline__ S enc(R v, int) { return v; }
+    __device__ static __forceinline__ double dec64(S v, int) { return static_cast<double>(v); }
+    __device__ static __forceinline__ S enc64(double v, int) { return static_cast<float>(v); }
+};
+
+template <> struct Form<F64> {
+    using S = double;
+    using R = double;
+    static constexpr int bytes = 8;
+    __device__ static __forceinline__ R dec(S v, int) { return v; }
+    __device__ static __forceinline__ S enc(R v, int) { return v; }
+    __device__ static __forceinline__ double dec64(S v, int) { return v; }
+    __device__ static __forceinline__ S enc64(double v, int) { return v; }
+};
+
+// ------------------------------------------------------------------- arithmetic
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// reciprocal: v_rcp_f32 (1 ulp) in FP32, correctly rounded division in FP64
+__device__ __forceinline__ float rcpR(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ double rcpR(double a) { return 1.0 / a; }
+__device__ __forceinline__ float divR(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double divR(double a, double b) { return a / b; }
+
+template <typename R> struct Coef {
+    R beta;            // relaxation parameter
+    R inv_beta;        // 1 / beta
+    R two_m_inv_beta;  // 2 - 1 / beta
+    R rho0;            // reference density of the deviation storage
+    R guard;           // gamma = 2 where <dh|dh> <= guard <ds|ds>
+    R gamma_fixed;     // stabiliser for GFIX
+};
+
+// Populations of a zero-mass, zero-momentum moment vector (T, N, Pi, Q_xyy,
+// Q_yxx, A) (density-weighted), eq. (momentsD2Q9).
+template <typename R>
+__device__ __forceinline__ void moments_to_pop(R T, R N, R P, R Qx, R Qy, R A, R (&p)[9]) {
+    const R h = R(0.5), q = R(0.25);
+    const R tp = q * (T + N), tm = q * (T - N);
+    p[0] = A - T;
+    p[1] = tp - h * (Qx + A);
+    p[3] = tp + h * (Qx - A);
+    p[2] = tm - h * (Qy + A);
+    p[4] = tm + h * (Qy - A);
+    const R ap = A + P, am = A - P;
+    p[5] = q * (ap + (Qx + Qy));
+    p[7] = q * (ap - (Qx + Qy));
+    p[6] = q * (am - (Qx - Qy));
+    p[8] = q * (am + (Qx - Qy));
+}
+
+// One collision on the deviations g (in place).  Returns the gamma used.
+template <typename R, int COLL, int VAR, int GM>
+__device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
+    const R s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
+    const R d13 = g[1] - g[3], d24 = g[2] - g[4], d57 = g[5] - g[7], d68 = g[6] - g[8];
+    const R sd = s57 + s68;
+    const R dr = (g[0] + sd) + (s13 + s24);        // rho - rho0
+    const R jx = d13 + (d57 - d68);                // rho u_x
+    const R jy = d24 + (d57 + d68);                // rho u_y
+    const R rho = K.rho0 + dr;
+    const R ir = rcpR(rho);
+    const R ux = jx * ir, uy = jy * ir;
+    const R uxx = ux * ux, uyy = uy * uy, u2 = uxx + uyy;
+
+    // e_i with feq_i = W_i rho (1 + e_i): e_i = 3 (v.u) + 4.5 (v.u)^2 - 1.5 |u|^2
+    const R c0 = R(-1.5) * u2;
+    const R upv = ux + uy, umv = ux - uy;
+    const R bx = fmaR(R(4.5), uxx, c0), by = fmaR(R(4.5), uyy, c0);
+    const R bp = fmaR(R(4.5) * upv, upv, c0), bm = fmaR(R(4.5) * umv, umv, c0);
+    R e[9];
+    e[0] = c0;
+    e[1] = fmaR(R(3), ux, bx);
+    e[3] = fmaR(R(-3), ux, bx);
+    e[2] = fmaR(R(3), uy, by);
+    e[4] = fmaR(R(-3), uy, by);
+    e[5] = fmaR(R(3), upv, bp);
+    e[7] = fmaR(R(-3), upv, bp);
+    e[8] = fmaR(R(3), umv, bm);
+    e[6] = fmaR(R(-3), umv, bm);
+
+    if constexpr (COLL == LBGK) {
+        // f' = f - 2 beta (f - feq), eq. (LBGKmirr) in eq. (Egeneral)
+        const R tb = R(2) * K.beta;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const R feqd = R(weight(i)) * fmaR(rho, e[i], dr);   // feq_i - W_i rho0
+            g[i] = fmaR(-tb, g[i] - feqd, g[i]);
+        }
+        return R(2);
+    } else {
+        const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
+        const R jux = jx * ux, juy = jy * uy;
+        const R dr3 = dr * third;
+        // non-equilibrium moments of df = f - feq
+        const R dPxx = ((s13 + sd) - dr3) - jux;
+        const R dPyy = ((s24 + sd) - dr3) - juy;
+        const R dPxy = (s57 - s68) - jx * uy;
+        const R dQx = (d57 - d68) - jx * third;
+        const R dQy = (d57 + d68) - jy * third;
+        const R dA = (sd - dr * ninth) - (jux + juy) * third;
+        const R dT = dPxx + dPyy, dN = dPxx - dPyy, dP = dPxy;
+
+        // shear part (s) and higher-order part (h) moments, Table kbc_moment_grouping
+        R Ts, Qxs, Qys, As;
+        if constexpr (VAR == VC) {
+            Ts = dT; Qxs = R(0); Qys = R(0); As = R(0);
+        } else if constexpr (VAR == VD) {
+            Ts = R(0); Qxs = R(0); Qys = R(0); As = R(0);
+        } else {
+            // linear part of eq. (cm) applied to the central shear moments
+            const R tT = (VAR == VA) ? dT : R(0);
+            const R hux = R(0.5) * ux, huy = R(0.5) * uy;
+            Ts = tT;
+            Qxs = fmaR(R(2) * uy, dP, hux * (tT - dN));
+            Qys = fmaR(R(2) * ux, dP, huy * (tT + dN));
+            As = fmaR(R(4) * ux * uy, dP, fmaR(R(0.5) * u2, tT, R(-0.5) * (uxx - uyy) * dN));
+        }
+        R ds[9], dh[9];
+        moments_to_pop<R>(Ts, dN, dP, Qxs, Qys, As, ds);
+        moments_to_pop<R>(dT - Ts, R(0), R(0), dQx - Qxs, dQy - Qys, dA - As, dh);
+
+        R gam;
+        if constexpr (GM == GFIX) {
+            gam = K.gamma_fixed;
+        } else {
+            // entropic scalar products with weights 1 / (W_i (1 + e_i))
+            R a = R(0), b = R(0), c = R(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const R w = R(inv_weight(i)) * rcpR(R(1) + e[i]);
+                const R wh = dh[i] * w;
+                a = fmaR(ds[i], wh, a);
+                b = fmaR(dh[i], wh, b);
+                c = fmaR(ds[i] * w, ds[i], c);
+            }
+            const R gs = fmaR(-K.two_m_inv_beta, divR(a, b), K.inv_beta);
+            gam = (b <= K.guard * c) ? R(2) : gs;
+        }
+        // f' = f - beta (2 ds + gamma dh), eqs. (Egeneral), (ksh-mirror)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = fmaR(-K.beta, fmaR(gam, dh[i], R(2) * ds[i]), g[i]);
+        return gam;
+    }
+}
+
+}  // namespace kbc

@@ -1,0 +1,92 @@
+// kbc_launch.hpp -- host-side launch interface between the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kbc_device.hpp"
+
+namespace kbc {
+
+// Everything a kernel launch needs about one lattice.
+struct Lattice {
+    int nx, ny;
+    int64_t pitch;          // elements per row
+    int form, collision, variant, gamma_mode;
+    double beta, rho0, guard, gamma_fixed;
+    hipStream_t stream;
+};
+
+// step kernel shapes (see kbc_step.hip)
+struct StepShape {
+    int rows;   // rows per workgroup tile: the tile is 64 x rows nodes, 4 waves
+};
+
+int launch_step(const Lattice& L, const void* src, void* dst, const StepShape& shape);
+int launch_init(const Lattice& L, void* dst, const double* rho, const double* ux, const double* uy,
+                const double* grad, int mode);
+int launch_moments(const Lattice& L, const void* src, double* rho, double* ux, double* uy,
+                   double* gamma);
+int launch_get_pop(const Lattice& L, const void* src, double* f);
+int launch_set_pop(const Lattice& L, void* dst, const double* f);
+
+// diagnostics: three passes writing per-block FP64 partials (kDiagSlots each)
+constexpr int kDiagSlots = 16;
+constexpr int kDiagBlocks = 1024;
+int launch_diag(const Lattice& L, const void* src, double* ux_s, double* uy_s, double* w_s,
+                double* partials);
+
+int launch_copy(void* dst, const void* src, size_t n_words, hipStream_t stream);
+
+// kernel-name lookup for profiling output
+const char* step_kernel_name(const Lattice& L);
+
+template <typename R>
+inline Coef<R> make_coef(const Lattice& L) {
+    Coef<R> k;
+    k.beta = static_cast<R>(L.beta);
+    k.inv_beta = static_cast<R>(1.0 / L.beta);
+    k.two_m_inv_beta = static_cast<R>(2.0 - 1.0 / L.beta);
+    k.rho0 = static_cast<R>(L.rho0);
+    k.guard = static_cast<R>(L.guard);
+    k.gamma_fixed = static_cast<R>(L.gamma_fixed);
+    return k;
+}
+
+// Calls Op<FORM, COLL, VAR, GM>::run(args...) for the lattice's configuration.
+// LBGK ignores the variant and the stabiliser mode.  Returns -5 for
+// combinations that are not built.
+template <template <int, int, int, int> class Op, int F, int V, typename... A>
+int dispatch_gm(int gm, A&&... a) {
+    switch (gm) {
+        case GEST: return Op<F, KBCC, V, GEST>::run(a...);
+        case GFIX: return Op<F, KBCC, V, GFIX>::run(a...);
+        default: return -5;
+    }
+}
+template <template <int, int, int, int> class Op, int F, typename... A>
+int dispatch_var(int var, int gm, A&&... a) {
+    switch (var) {
+        case VA: return dispatch_gm<Op, F, VA>(gm, a...);
+        case VB: return dispatch_gm<Op, F, VB>(gm, a...);
+        case VC: return dispatch_gm<Op, F, VC>(gm, a...);
+        case VD: return dispatch_gm<Op, F, VD>(gm, a...);
+        default: return -1;
+    }
+}
+template <template <int, int, int, int> class Op, int F, typename... A>
+int dispatch_coll(int coll, int var, int gm, A&&... a) {
+    if (coll == LBGK) return Op<F, LBGK, VA, GEST>::run(a...);
+    return dispatch_var<Op, F>(var, gm, a...);
+}
+template <template <int, int, int, int> class Op, typename... A>
+int dispatch(const Lattice& L, A&&... a) {
+    switch (L.form) {
+        case F16: return dispatch_coll<Op, F16>(L.collision, L.variant, L.gamma_mode, L, a...);
+        case F32: return dispatch_coll<Op, F32>(L.collision, L.variant, L.gamma_mode, L, a...);
+        case F64: return dispatch_coll<Op, F64>(L.collision, L.variant, L.gamma_mode, L, a...);
+        default: return -1;
+    }
+}
+
+}  // namespace kbc

@@ -71,8 +71,10 @@ def _spectrum(k: np.ndarray, k0: float, kind: str) -> np.ndarray:
 
 
 def spectral(n: int, k0: float, u_rms: float, seed: int, kind: str = "gauss4",
-             kmax: int | None = None, ny: int | None = None):
-    """Divergence-free random velocity on an ``ny x n`` periodic grid (``ny`` defaults to n)."""
+             kmax: int | None = None, ny: int | None = None, device=None):
+    """Divergence-free random velocity on an ``ny x n`` periodic grid (``ny``
+    defaults to n).  With ``device`` set, the transforms run in torch on that
+    device and torch float64 tensors are returned (same coefficients)."""
     ny = n if ny is None else ny
     if kmax is None:
         kmax = int(np.ceil(4 * k0))
@@ -91,20 +93,35 @@ def spectral(n: int, k0: float, u_rms: float, seed: int, kind: str = "gauss4",
     coef = amp * (xi[0] + 1j * xi[1]) / np.sqrt(2.0)
     # Hermitian symmetrisation: psi_hat(-k) = conj(psi_hat(k)), so psi is real
     coef = 0.5 * (coef + np.conj(coef[::-1, ::-1]))
-    psi_hat = np.zeros((ny, n), dtype=np.complex128)
     iy = (kk.astype(np.int64)) % ny
     ix = (kk.astype(np.int64)) % n
-    psi_hat[np.ix_(iy, ix)] = coef
-    kx_l = 2.0 * np.pi * np.fft.fftfreq(n) * 1.0
-    ky_l = 2.0 * np.pi * np.fft.fftfreq(ny) * 1.0
-    KXl, KYl = np.meshgrid(kx_l, ky_l, indexing="xy")
-    ux = np.real(np.fft.ifft2(1j * KYl * psi_hat))
-    uy = np.real(np.fft.ifft2(-1j * KXl * psi_hat))
-    rms = np.sqrt(np.mean(ux * ux + uy * uy))
+    if device is None:
+        psi_hat = np.zeros((ny, n), dtype=np.complex128)
+        psi_hat[np.ix_(iy, ix)] = coef
+        kx_l = 2.0 * np.pi * np.fft.fftfreq(n)
+        ky_l = 2.0 * np.pi * np.fft.fftfreq(ny)
+        ux = np.real(np.fft.ifft2(1j * ky_l[:, None] * psi_hat))
+        uy = np.real(np.fft.ifft2(-1j * kx_l[None, :] * psi_hat))
+        rms = np.sqrt(np.mean(ux * ux + uy * uy))
+        if rms == 0.0:
+            raise ValueError("degenerate spectral field")
+        s = u_rms / rms
+        return np.ascontiguousarray(ux * s), np.ascontiguousarray(uy * s)
+    import torch
+    psi_hat = torch.zeros((ny, n), dtype=torch.complex128, device=device)
+    iyt = torch.as_tensor(iy, device=device)
+    ixt = torch.as_tensor(ix, device=device)
+    psi_hat[iyt[:, None], ixt[None, :]] = torch.as_tensor(coef, device=device)
+    kx_l = 2.0 * np.pi * torch.fft.fftfreq(n, device=device, dtype=torch.float64)
+    ky_l = 2.0 * np.pi * torch.fft.fftfreq(ny, device=device, dtype=torch.float64)
+    ux = torch.fft.ifft2(1j * ky_l[:, None] * psi_hat).real.contiguous()
+    uy = torch.fft.ifft2(-1j * kx_l[None, :] * psi_hat).real.contiguous()
+    del psi_hat
+    rms = torch.sqrt(torch.mean(ux * ux + uy * uy)).item()
     if rms == 0.0:
         raise ValueError("degenerate spectral field")
     s = u_rms / rms
-    return np.ascontiguousarray(ux * s), np.ascontiguousarray(uy * s)
+    return ux.mul_(s), uy.mul_(s)
 
 
 def shear_layer(n: int, u0: float = 0.04, kappa: float = 80.0, delta: float = 0.05):

@@ -1,0 +1,146 @@
+"""A lattice on one GPU behind the C ABI: torch allocates the population
+buffers and the macroscopic fields and provides the stream; libkbc does all
+of the work."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_FORMS = {"f16": L.F16DEV_F32, "f32": L.F32DEV_F32, "f64": L.F64}
+_TORCH_STORE = {L.F16DEV_F32: torch.float16, L.F32DEV_F32: torch.float32, L.F64: torch.float64}
+_VARIANTS = {"A": L.KBC_A, "B": L.KBC_B, "C": L.KBC_C, "D": L.KBC_D}
+_GMODES = {"estimate": L.GAMMA_ESTIMATE, "fixed": L.GAMMA_FIXED, "exact": L.GAMMA_EXACT}
+_INIT = {"eq": L.INIT_EQ, "grad_cd": L.INIT_GRAD_CD, "grad_given": L.INIT_GRAD_GIVEN}
+
+
+def beta_from_nu(nu: float) -> float:
+    """beta from the kinematic viscosity, eq. (viscosity) with cs2 = 1/3."""
+    return 1.0 / (6.0 * nu + 1.0)
+
+
+def _dev64(a, device) -> torch.Tensor | None:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+    return a.to(device=device, dtype=torch.float64).contiguous()
+
+
+class Sim:
+    """One periodic nx x ny lattice.
+
+    collision: "kbc" or "lbgk"; variant: "A".."D" (Table kbc_moment_grouping);
+    form: "f16" | "f32" | "f64" (storage form, see include/kbc.h).
+    """
+
+    def __init__(self, nx: int, ny: int, beta: float, collision: str = "kbc", variant: str = "B",
+                 form: str = "f32", gamma_mode: str = "estimate", gamma_guard: float = 1e-12,
+                 gamma_fixed: float = 2.0, rho0: float = 1.0, device="cuda:0", tile: int | None = None):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.nx, self.ny = int(nx), int(ny)
+        self.form = _FORMS[form]
+        self.pitch = int(self.lib.lbm_required_pitch(self.nx, self.form))
+        if self.pitch == 0:
+            raise ValueError("invalid lattice size or form")
+        dt = _TORCH_STORE[self.form]
+        self.buf_a = torch.empty((9, self.ny, self.pitch), dtype=dt, device=self.device)
+        self.buf_b = torch.empty((9, self.ny, self.pitch), dtype=dt, device=self.device)
+        self.params = L.Params()
+        self.params.nx, self.params.ny = self.nx, self.ny
+        self.params.beta = float(beta)
+        self.params.rho0 = float(rho0)
+        self.params.collision = L.LBGK if collision.lower() == "lbgk" else L.KBC
+        self.params.variant = _VARIANTS[variant.upper()]
+        self.params.form = self.form
+        self.params.gamma_mode = _GMODES[gamma_mode]
+        self.params.gamma_guard = float(gamma_guard)
+        self.params.gamma_fixed = float(gamma_fixed)
+        self.params.stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.ctx = ctypes.c_void_p()
+        self._tile = tile
+        self._inputs = None
+
+    # ------------------------------------------------------------------ setup
+    def init(self, ux, uy, rho=None, mode: str = "grad_cd", grad=None) -> "Sim":
+        ux, uy = _dev64(ux, self.device), _dev64(uy, self.device)
+        rho, grad = _dev64(rho, self.device), _dev64(grad, self.device)
+        for a in (ux, uy):
+            assert a.shape == (self.ny, self.nx), "velocity fields must be [ny, nx]"
+        if self.ctx:
+            self.free()
+        L.check(self.lib.lbm_init(ctypes.byref(self.ctx), ctypes.byref(self.params), L.ptr(self.buf_a),
+                                  L.ptr(self.buf_b), self.pitch, L.ptr(rho), L.ptr(ux), L.ptr(uy),
+                                  L.ptr(grad), _INIT[mode]), "lbm_init")
+        self._inputs = (ux, uy, rho, grad)   # alive until the init kernel has run
+        if self._tile is not None:
+            self.set_tile(self._tile)
+        return self
+
+    def set_tile(self, rows: int):
+        L.check(self.lib.lbm_set_tile(self.ctx, int(rows)), "lbm_set_tile")
+
+    def set_beta(self, beta: float):
+        self.params.beta = float(beta)
+        if self.ctx:
+            L.check(self.lib.lbm_set_beta(self.ctx, float(beta)), "lbm_set_beta")
+
+    # ------------------------------------------------------------------- run
+    def step(self, n: int = 1) -> "Sim":
+        L.check(self.lib.lbm_step(self.ctx, int(n)), "lbm_step")
+        return self
+
+    @property
+    def steps(self) -> int:
+        return int(self.lib.lbm_step_count(self.ctx))
+
+    def moments(self, gamma: bool = False):
+        shape = (self.ny, self.nx)
+        rho, ux, uy = (torch.empty(shape, dtype=torch.float64, device=self.device) for _ in range(3))
+        g = torch.empty(shape, dtype=torch.float64, device=self.device) if gamma else None
+        L.check(self.lib.lbm_moments(self.ctx, L.ptr(rho), L.ptr(ux), L.ptr(uy), L.ptr(g)), "lbm_moments")
+        return (rho, ux, uy, g) if gamma else (rho, ux, uy)
+
+    def get_populations(self) -> torch.Tensor:
+        f = torch.empty((9, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        L.check(self.lib.lbm_get_populations(self.ctx, L.ptr(f)), "lbm_get_populations")
+        return f
+
+    def set_populations(self, f):
+        f = _dev64(f, self.device)
+        assert f.shape == (9, self.ny, self.nx)
+        L.check(self.lib.lbm_set_populations(self.ctx, L.ptr(f)), "lbm_set_populations")
+        self._inputs = (f,)
+
+    def diagnostics(self) -> dict:
+        d = L.Diag()
+        L.check(self.lib.lbm_diagnostics(self.ctx, ctypes.byref(d)), "lbm_diagnostics")
+        return {k: getattr(d, k) for k in L.DIAG_FIELDS if k != "reserved"}
+
+    def state_buffer(self) -> torch.Tensor:
+        p = self.lib.lbm_state_buffer(self.ctx)
+        return self.buf_a if p == self.buf_a.data_ptr() else self.buf_b
+
+    def free(self):
+        if self.ctx:
+            L.check(self.lib.lbm_free(self.ctx), "lbm_free")
+            self.ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self.ctx and L._lib is not None:
+                L._lib.lbm_free(self.ctx)
+        except Exception:
+            pass
+
+
+def copy_probe(dst: torch.Tensor, src: torch.Tensor):
+    """dst <- src through the library's streaming copy kernel (4-byte words)."""
+    lib = L.load()
+    n = src.numel() * src.element_size() // 4
+    L.check(lib.lbm_copy_probe(L.ptr(dst), L.ptr(src), n, torch.cuda.current_stream(dst.device).cuda_stream),
+            "lbm_copy_probe")
