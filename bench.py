@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--variant", default="B")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extra-steps", type=int, default=50,
+                    help="timed steps for the other forms and the LBGK baseline")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -160,14 +162,14 @@ def main():
             if form == args.form:
                 continue
             s = make_sim(n, form, "kbc", args.variant, nu, seed, k0, dev)
-            m, _ = time_steps(s, 50, 5)
+            m, _ = time_steps(s, args.extra_steps, 2)
             del s
             torch.cuda.empty_cache()
             extras[f"kbc{args.variant}_{form}"] = {
                 "mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4),
                 "hbm_frac": round(BYTES_PER_NODE[form] * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         s = make_sim(n, args.form, "lbgk", "A", nu, seed, k0, dev)
-        m, _ = time_steps(s, 50, 5)
+        m, _ = time_steps(s, args.extra_steps, 2)
         del s
         torch.cuda.empty_cache()
         extras[f"lbgk_{args.form}"] = {"mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4)}

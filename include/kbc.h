@@ -151,10 +151,14 @@ int lbm_set_step(lbm_ctx* c, int64_t n);
 void* lbm_state_buffer(const lbm_ctx* c);
 void* lbm_work_buffer(const lbm_ctx* c);
 
-/* Workgroup tile of the step kernel: 64 x `rows` nodes, rows in {4, 8, 16}
- * (default 4).  A tuning knob only: results are bitwise identical for every
- * tile. */
-int lbm_set_tile(lbm_ctx* c, int32_t rows);
+/* Workgroup tile of the step kernel: `width` in {64, 128, 256} nodes by
+ * (256 / width) * rows_per_thread rows, rows_per_thread in {1, 2, 4}
+ * (default per form: 64 x 16 non-temporal for FP16, 256 x 2 for FP32,
+ * 256 x 2 non-temporal for FP64); flags: LBM_TILE_NONTEMPORAL writes the new state with
+ * non-temporal stores.  A tuning knob only: results are bitwise identical for
+ * every setting. */
+#define LBM_TILE_NONTEMPORAL 1
+int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t flags);
 
 /* Replace beta (e.g. between rollouts); other parameters are fixed per ctx. */
 int lbm_set_beta(lbm_ctx* c, double beta);

@@ -74,6 +74,18 @@ int check_params(const lbm_params* p) {
     return LBM_OK;
 }
 
+// Default step tile per storage form, from a sweep on MI355X at 16384^2
+// (the autotuner in the Python package can replace it per lattice).
+kbc::StepShape default_shape(int32_t form) {
+    kbc::StepShape s;
+    switch (form) {
+        case LBM_F16DEV_F32: s.width = 64; s.rpt = 4; s.nt = 1; break;
+        case LBM_F64: s.width = 256; s.rpt = 2; s.nt = 1; break;
+        default: s.width = 256; s.rpt = 2; s.nt = 0; break;
+    }
+    return s;
+}
+
 kbc::Lattice lattice_of(const lbm_params& p, size_t pitch) {
     kbc::Lattice L;
     L.nx = p.nx;
@@ -135,7 +147,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     c->buf[1] = buf_b;
     c->cur = 0;
     c->steps = 0;
-    c->shape.rows = 4;
+    c->shape = default_shape(p->form);
     c->dscratch = nullptr;
     c->dscratch_elems = 0;
     rc = kbc::launch_init(c->L, buf_a, rho, ux, uy, grad, mode);
@@ -244,10 +256,15 @@ int lbm_set_step(lbm_ctx* c, int64_t n) {
 void* lbm_state_buffer(const lbm_ctx* c) { return c ? c->buf[c->cur] : nullptr; }
 void* lbm_work_buffer(const lbm_ctx* c) { return c ? c->buf[c->cur ^ 1] : nullptr; }
 
-int lbm_set_tile(lbm_ctx* c, int32_t rows) {
+int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t flags) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-    if (rows != 4 && rows != 8 && rows != 16) return fail(LBM_EINVAL, "tile rows must be 4, 8 or 16");
-    c->shape.rows = rows;
+    kbc::StepShape s;
+    s.width = width;
+    s.rpt = rows_per_thread;
+    s.nt = (flags & LBM_TILE_NONTEMPORAL) ? 1 : 0;
+    if ((flags & ~LBM_TILE_NONTEMPORAL) != 0) return fail(LBM_EINVAL, "unknown tile flags %d", flags);
+    if (!kbc::valid_shape(s)) return fail(LBM_EINVAL, "tile width must be 64, 128 or 256 and rows per thread 1, 2 or 4");
+    c->shape = s;
     return LBM_OK;
 }
 

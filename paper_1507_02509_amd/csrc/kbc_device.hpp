@@ -130,24 +130,24 @@ __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
     const R ux = jx * ir, uy = jy * ir;
     const R uxx = ux * ux, uyy = uy * uy, u2 = uxx + uyy;
 
-    // e_i with feq_i = W_i rho (1 + e_i): e_i = 3 (v.u) + 4.5 (v.u)^2 - 1.5 |u|^2
-    const R c0 = R(-1.5) * u2;
     const R upv = ux + uy, umv = ux - uy;
-    const R bx = fmaR(R(4.5), uxx, c0), by = fmaR(R(4.5), uyy, c0);
-    const R bp = fmaR(R(4.5) * upv, upv, c0), bm = fmaR(R(4.5) * umv, umv, c0);
-    R e[9];
-    e[0] = c0;
-    e[1] = fmaR(R(3), ux, bx);
-    e[3] = fmaR(R(-3), ux, bx);
-    e[2] = fmaR(R(3), uy, by);
-    e[4] = fmaR(R(-3), uy, by);
-    e[5] = fmaR(R(3), upv, bp);
-    e[7] = fmaR(R(-3), upv, bp);
-    e[8] = fmaR(R(3), umv, bm);
-    e[6] = fmaR(R(-3), umv, bm);
-
     if constexpr (COLL == LBGK) {
-        // f' = f - 2 beta (f - feq), eq. (LBGKmirr) in eq. (Egeneral)
+        // f' = f - 2 beta (f - feq), eq. (LBGKmirr) in eq. (Egeneral), with
+        // feq_i - W_i rho0 = W_i [ (rho - rho0) + rho e_i ],
+        // e_i = 3 (v.u) + 4.5 (v.u)^2 - 1.5 |u|^2
+        const R c0 = R(-1.5) * u2;
+        const R bx = fmaR(R(4.5), uxx, c0), by = fmaR(R(4.5), uyy, c0);
+        const R bp = fmaR(R(4.5) * upv, upv, c0), bm = fmaR(R(4.5) * umv, umv, c0);
+        R e[9];
+        e[0] = c0;
+        e[1] = fmaR(R(3), ux, bx);
+        e[3] = fmaR(R(-3), ux, bx);
+        e[2] = fmaR(R(3), uy, by);
+        e[4] = fmaR(R(-3), uy, by);
+        e[5] = fmaR(R(3), upv, bp);
+        e[7] = fmaR(R(-3), upv, bp);
+        e[8] = fmaR(R(3), umv, bm);
+        e[6] = fmaR(R(-3), umv, bm);
         const R tb = R(2) * K.beta;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -191,11 +191,27 @@ __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
         if constexpr (GM == GFIX) {
             gam = K.gamma_fixed;
         } else {
-            // entropic scalar products with weights 1 / (W_i (1 + e_i))
+            // entropic scalar products, weights 1 / (W_i (1 + e_i)) = rho / feq_i;
+            // d_i = W_i (1 + e_i) = W_i (1 - 1.5 |u|^2 + 4.5 (v.u)^2) + 3 W_i (v.u)
+            const R d0 = fmaR(R(-2.0 / 3.0), u2, R(4.0 / 9.0));
+            const R a1 = fmaR(R(-1.0 / 6.0), u2, R(1.0 / 9.0));
+            const R a5 = fmaR(R(-1.0 / 24.0), u2, R(1.0 / 36.0));
+            const R dx = fmaR(R(0.5), uxx, a1), dy = fmaR(R(0.5), uyy, a1);
+            const R dp = fmaR(R(0.125) * upv, upv, a5), dm = fmaR(R(0.125) * umv, umv, a5);
+            R d[9];
+            d[0] = d0;
+            d[1] = fmaR(R(1.0 / 3.0), ux, dx);
+            d[3] = fmaR(R(-1.0 / 3.0), ux, dx);
+            d[2] = fmaR(R(1.0 / 3.0), uy, dy);
+            d[4] = fmaR(R(-1.0 / 3.0), uy, dy);
+            d[5] = fmaR(R(1.0 / 12.0), upv, dp);
+            d[7] = fmaR(R(-1.0 / 12.0), upv, dp);
+            d[8] = fmaR(R(1.0 / 12.0), umv, dm);
+            d[6] = fmaR(R(-1.0 / 12.0), umv, dm);
             R a = R(0), b = R(0), c = R(0);
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const R w = R(inv_weight(i)) * rcpR(R(1) + e[i]);
+                const R w = rcpR(d[i]);
                 const R wh = dh[i] * w;
                 a = fmaR(ds[i], wh, a);
                 b = fmaR(dh[i], wh, b);
@@ -205,8 +221,9 @@ __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
             gam = (b <= K.guard * c) ? R(2) : gs;
         }
         // f' = f - beta (2 ds + gamma dh), eqs. (Egeneral), (ksh-mirror)
+        const R tb = R(2) * K.beta, bg = K.beta * gam;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = fmaR(-K.beta, fmaR(gam, dh[i], R(2) * ds[i]), g[i]);
+        for (int i = 0; i < 9; ++i) g[i] = fmaR(-bg, dh[i], fmaR(-tb, ds[i], g[i]));
         return gam;
     }
 }

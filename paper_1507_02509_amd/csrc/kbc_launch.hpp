@@ -17,10 +17,15 @@ struct Lattice {
     hipStream_t stream;
 };
 
-// step kernel shapes (see kbc_step.hip)
+// step kernel tile: `width` in {64, 128, 256} nodes, each thread walks `rpt`
+// in {1, 2, 4} rows; the tile is width x (256 / width) * rpt nodes; `nt`
+// selects non-temporal stores
 struct StepShape {
-    int rows;   // rows per workgroup tile: the tile is 64 x rows nodes, 4 waves
+    int width;
+    int rpt;
+    int nt;
 };
+bool valid_shape(const StepShape& s);
 
 int launch_step(const Lattice& L, const void* src, void* dst, const StepShape& shape);
 int launch_init(const Lattice& L, void* dst, const double* rho, const double* ux, const double* uy,

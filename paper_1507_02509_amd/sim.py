@@ -39,7 +39,8 @@ class Sim:
 
     def __init__(self, nx: int, ny: int, beta: float, collision: str = "kbc", variant: str = "B",
                  form: str = "f32", gamma_mode: str = "estimate", gamma_guard: float = 1e-12,
-                 gamma_fixed: float = 2.0, rho0: float = 1.0, device="cuda:0", tile: int | None = None):
+                 gamma_fixed: float = 2.0, rho0: float = 1.0, device="cuda:0", tile: tuple | None = None,
+                 pitch_pad: int = 0):
         self.lib = L.load()
         self.device = torch.device(device)
         self.nx, self.ny = int(nx), int(ny)
@@ -47,6 +48,9 @@ class Sim:
         self.pitch = int(self.lib.lbm_required_pitch(self.nx, self.form))
         if self.pitch == 0:
             raise ValueError("invalid lattice size or form")
+        if pitch_pad % 64:
+            raise ValueError("pitch_pad must be a multiple of 64 elements")
+        self.pitch += int(pitch_pad)
         dt = _TORCH_STORE[self.form]
         self.buf_a = torch.empty((9, self.ny, self.pitch), dtype=dt, device=self.device)
         self.buf_b = torch.empty((9, self.ny, self.pitch), dtype=dt, device=self.device)
@@ -78,11 +82,12 @@ class Sim:
                                   L.ptr(grad), _INIT[mode]), "lbm_init")
         self._inputs = (ux, uy, rho, grad)   # alive until the init kernel has run
         if self._tile is not None:
-            self.set_tile(self._tile)
+            self.set_tile(*self._tile)
         return self
 
-    def set_tile(self, rows: int):
-        L.check(self.lib.lbm_set_tile(self.ctx, int(rows)), "lbm_set_tile")
+    def set_tile(self, width: int, rows_per_thread: int = 1, nontemporal: bool = False):
+        L.check(self.lib.lbm_set_tile(self.ctx, int(width), int(rows_per_thread), 1 if nontemporal else 0),
+                "lbm_set_tile")
 
     def set_beta(self, beta: float):
         self.params.beta = float(beta)

@@ -221,8 +221,8 @@ def test_tile_shapes_are_bitwise_identical(form, coll, var):
     say("tile shapes", form, coll, var)
     ux, uy = inputs.spectral(nx, 4, 0.05, seed=20, ny=ny)
     outs = []
-    for rows in (4, 8, 16):
-        s = Sim(nx, ny, beta_from_nu(1e-4), collision=coll, variant=var, form=form, tile=rows)
+    for tile in ((64, 1, False), (64, 4, True), (128, 2, False), (256, 1, True), (256, 4, False)):
+        s = Sim(nx, ny, beta_from_nu(1e-4), collision=coll, variant=var, form=form, tile=tile)
         s.init(ux, uy)
         s.step(7)
         outs.append(s.state_buffer()[:, :, :nx].clone())
