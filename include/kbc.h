@@ -170,6 +170,53 @@ int lbm_free(lbm_ctx* c);
 /* Message of the last failed call on this thread ("" if none). */
 const char* lbm_last_error(void);
 
+/* ------------------------------------------------------------------ adjoint
+ * Gradients of a loss of the final state with respect to the initial
+ * velocity and beta (discrete adjoint of eq. (Egeneral) with the collision of
+ * this context, gamma(f) of eq. (result21) differentiated; constant where the
+ * guard selects gamma = 2).  An adjoint buffer holds dL/df for every node and
+ * velocity, [9][ny][pitch] in the form's arithmetic type (float for the two
+ * deviation forms, double for LBM_F64), NOT shifted: element (i, y, x) is
+ * dL/df_i(x, y).  `state` arguments are population buffers in this context's
+ * layout holding f(x, t = n) (e.g. checkpoints copied from lbm_state_buffer).
+ * Derivatives of beta are added (+=) to the device double *dbeta when it is
+ * not NULL, in a fixed summation order (bitwise reproducible). */
+
+/* How the adjoint step treats the stabiliser: LBM_ADJ_GAMMA_FULL (default)
+ * differentiates gamma(f) of eq. (result21); LBM_ADJ_GAMMA_FROZEN holds it at
+ * the forward value (derivative of the map with gamma a per-node constant).
+ * The exact derivative of gamma* carries factors 1 / <dh|dh>, large where dh
+ * is small but above the guard, so over long turbulent rollouts the full
+ * adjoint can grow far beyond the finite-difference slope of the loss. */
+#define LBM_ADJ_GAMMA_FULL 0
+#define LBM_ADJ_GAMMA_FROZEN 1
+int lbm_set_adjoint_gamma(lbm_ctx* c, int32_t mode);
+
+/* Bytes of one adjoint buffer. */
+size_t lbm_adjoint_bytes(int32_t nx, int32_t ny, int32_t form);
+
+/* One forward step from population buffer src into dst (neither is the
+ * context's own state unless the caller passes it); used to recompute states
+ * between checkpoints. */
+int lbm_step_buffers(lbm_ctx* c, const void* src, void* dst);
+
+/* lam = dL/df for a loss of the moments of `state`: given dL/drho, dL/du_x,
+ * dL/du_y (dense FP64 [ny][nx] device arrays, each nullable = 0),
+ * lam_i(x) = dL/drho + (dL/du_x (v_xi - u_x) + dL/du_y (v_yi - u_y)) / rho. */
+int lbm_adjoint_seed(lbm_ctx* c, const void* state, const double* dL_drho, const double* dL_dux,
+                     const double* dL_duy, void* lam);
+
+/* One adjoint step: with state = f^n and lam_in = dL/df^{n+1}, writes
+ * lam_out = dL/df^n and adds the step's dL/dbeta to *dbeta. */
+int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta);
+
+/* Adjoint of lbm_init for modes LBM_INIT_EQ and LBM_INIT_GRAD_CD: from
+ * lam0 = dL/df^0 and the initial fields (rho nullable = rho0), writes
+ * dL/du_x, dL/du_y (dense FP64 [ny][nx]) and adds dL/dbeta of the initial
+ * state (through Pi^(1), eq. P1AC) to *dbeta. */
+int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, int32_t mode,
+                     const void* lam0, double* grad_ux, double* grad_uy, double* dbeta);
+
 /* Streaming copy dst[i] = src[i] of n 4-byte words on `stream`: the bandwidth
  * reference measured beside the step. */
 int lbm_copy_probe(void* dst, const void* src, size_t n_words, void* stream);

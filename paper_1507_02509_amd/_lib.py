@@ -67,6 +67,12 @@ _SIGS = {
     "lbm_free": (_c.c_int, [_vp]),
     "lbm_last_error": (_c.c_char_p, []),
     "lbm_copy_probe": (_c.c_int, [_vp, _vp, _c.c_size_t, _vp]),
+    "lbm_set_adjoint_gamma": (_c.c_int, [_vp, _c.c_int32]),
+    "lbm_adjoint_bytes": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),
+    "lbm_step_buffers": (_c.c_int, [_vp, _vp, _vp]),
+    "lbm_adjoint_seed": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "lbm_adjoint_step": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "lbm_adjoint_init": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int32, _vp, _vp, _vp, _vp]),
 }
 
 

@@ -1,0 +1,243 @@
+// kbc_adjoint.hpp -- reverse-mode derivative (vector-Jacobian product) of the
+// per-node collision of kbc_device.hpp.
+//
+// Given the deviations g of a pre-collision state and the adjoint mu of the
+// post-collision deviations, collide_vjp returns lam = J^T mu, J = dg'/dg, and
+// the node's contribution mu . dg'/dbeta.  The stabiliser gamma(f) of
+// eq. (result21) is by default differentiated with the rest of the collision through
+// <ds|dh>, <dh|dh> and the entropic weights 1/feq; where the denominator guard
+// selects gamma = 2 it is a constant.  The forward quantities are recomputed
+// with exactly the operations of collide(), then the chain rule runs through
+// them in reverse order.
+#pragma once
+
+#include "kbc_device.hpp"
+
+namespace kbc {
+
+// Adjoint of moments_to_pop: moment adjoints from population adjoints pb.
+template <typename R>
+__device__ __forceinline__ void pop_to_moments_adj(const R (&pb)[9], R& Tb, R& Nb, R& Pb, R& Qxb,
+                                                   R& Qyb, R& Ab) {
+    const R q = R(0.25), h = R(0.5);
+    const R ax = pb[1] + pb[3], ay = pb[2] + pb[4];
+    const R dg = (pb[5] + pb[7]) + (pb[6] + pb[8]);
+    Tb = q * (ax + ay) - pb[0];
+    Nb = q * (ax - ay);
+    Pb = q * ((pb[5] + pb[7]) - (pb[6] + pb[8]));
+    Qxb = h * (pb[3] - pb[1]) + q * ((pb[5] - pb[7]) - (pb[6] - pb[8]));
+    Qyb = h * (pb[4] - pb[2]) + q * ((pb[5] - pb[7]) + (pb[6] - pb[8]));
+    Ab = pb[0] - h * (ax + ay) + q * dg;
+}
+
+// FROZEN = true holds gamma at its forward value (the derivative of the map
+// with the stabiliser treated as a per-node constant).
+template <typename R, int COLL, int VAR, int GM, bool FROZEN = false>
+__device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], const Coef<R>& K,
+                                            R (&lam)[9], R& dbeta) {
+    // ------------------------------------------------ forward (as in collide)
+    const R s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
+    const R d13 = g[1] - g[3], d24 = g[2] - g[4], d57 = g[5] - g[7], d68 = g[6] - g[8];
+    const R sd = s57 + s68;
+    const R dr = (g[0] + sd) + (s13 + s24);
+    const R jx = d13 + (d57 - d68);
+    const R jy = d24 + (d57 + d68);
+    const R rho = K.rho0 + dr;
+    const R ir = rcpR(rho);
+    const R ux = jx * ir, uy = jy * ir;
+    const R uxx = ux * ux, uyy = uy * uy, u2 = uxx + uyy;
+    const R upv = ux + uy, umv = ux - uy;
+
+    // adjoints of rho - rho0, j and u collected below
+    R drb = R(0), jxb = R(0), jyb = R(0), uxb = R(0), uyb = R(0);
+    // adjoints of the raw sums of g: sum c_x^2 g, sum c_y^2 g, sum c_x c_y g,
+    // sum c_x c_y^2 g, sum c_x^2 c_y g, sum c_x^2 c_y^2 g
+    R Sxxb = R(0), Syyb = R(0), Sxyb = R(0), Qxrb = R(0), Qyrb = R(0), Arb = R(0);
+
+    if constexpr (COLL == LBGK) {
+        // g' = g - 2 beta (g - feqd); feqd_i = W_i [ (rho - rho0) + rho e_i ]
+        const R c0 = R(-1.5) * u2;
+        const R bx = fmaR(R(4.5), uxx, c0), by = fmaR(R(4.5), uyy, c0);
+        const R bp = fmaR(R(4.5) * upv, upv, c0), bm = fmaR(R(4.5) * umv, umv, c0);
+        R e[9];
+        e[0] = c0;
+        e[1] = fmaR(R(3), ux, bx);
+        e[3] = fmaR(R(-3), ux, bx);
+        e[2] = fmaR(R(3), uy, by);
+        e[4] = fmaR(R(-3), uy, by);
+        e[5] = fmaR(R(3), upv, bp);
+        e[7] = fmaR(R(-3), upv, bp);
+        e[8] = fmaR(R(3), umv, bm);
+        e[6] = fmaR(R(-3), umv, bm);
+        const R tb = R(2) * K.beta;
+        R db = R(0);
+        // feqd_i depends on dr (directly and through rho) and on u through e_i:
+        // d feqd_i / d dr = W_i (1 + e_i), d e_i / d u = 3 c_i + 9 (c_i.u) c_i - 3 u
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const R feqd = R(weight(i)) * fmaR(rho, e[i], dr);
+            db = fmaR(mu[i], g[i] - feqd, db);
+            const R fb = tb * mu[i];                 // adjoint of feqd_i
+            const R wr = R(weight(i)) * fb;
+            drb = fmaR(wr, R(1) + e[i], drb);
+            const R cu = R(kCx[i]) * ux + R(kCy[i]) * uy;
+            const R eb = wr * rho;                   // adjoint of e_i
+            uxb = fmaR(eb, fmaR(R(9) * cu, R(kCx[i]), fmaR(R(-3), ux, R(3) * R(kCx[i]))), uxb);
+            uyb = fmaR(eb, fmaR(R(9) * cu, R(kCy[i]), fmaR(R(-3), uy, R(3) * R(kCy[i]))), uyb);
+            lam[i] = (R(1) - tb) * mu[i];
+        }
+        dbeta = R(-2) * db;
+    } else {
+        const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
+        const R jux = jx * ux, juy = jy * uy;
+        const R dr3 = dr * third;
+        const R dPxx = ((s13 + sd) - dr3) - jux;
+        const R dPyy = ((s24 + sd) - dr3) - juy;
+        const R dPxy = (s57 - s68) - jx * uy;
+        const R dQx = (d57 - d68) - jx * third;
+        const R dQy = (d57 + d68) - jy * third;
+        const R dA = (sd - dr * ninth) - (jux + juy) * third;
+        const R dT = dPxx + dPyy, dN = dPxx - dPyy, dP = dPxy;
+        R Ts, Qxs, Qys, As;
+        R tT = R(0);
+        if constexpr (VAR == VC) {
+            Ts = dT; Qxs = R(0); Qys = R(0); As = R(0);
+        } else if constexpr (VAR == VD) {
+            Ts = R(0); Qxs = R(0); Qys = R(0); As = R(0);
+        } else {
+            tT = (VAR == VA) ? dT : R(0);
+            const R hux = R(0.5) * ux, huy = R(0.5) * uy;
+            Ts = tT;
+            Qxs = fmaR(R(2) * uy, dP, hux * (tT - dN));
+            Qys = fmaR(R(2) * ux, dP, huy * (tT + dN));
+            As = fmaR(R(4) * ux * uy, dP, fmaR(R(0.5) * u2, tT, R(-0.5) * (uxx - uyy) * dN));
+        }
+        R ds[9], dh[9];
+        moments_to_pop<R>(Ts, dN, dP, Qxs, Qys, As, ds);
+        moments_to_pop<R>(dT - Ts, R(0), R(0), dQx - Qxs, dQy - Qys, dA - As, dh);
+
+        R gam = R(2), ratio = R(0), bsum = R(1);
+        bool active = false;          // gamma depends on f
+        R d[9], w[9];
+        if constexpr (GM == GFIX) {
+            gam = K.gamma_fixed;
+        } else {
+            const R d0 = fmaR(R(-2.0 / 3.0), u2, R(4.0 / 9.0));
+            const R a1 = fmaR(R(-1.0 / 6.0), u2, R(1.0 / 9.0));
+            const R a5 = fmaR(R(-1.0 / 24.0), u2, R(1.0 / 36.0));
+            const R dx = fmaR(R(0.5), uxx, a1), dy = fmaR(R(0.5), uyy, a1);
+            const R dp = fmaR(R(0.125) * upv, upv, a5), dm = fmaR(R(0.125) * umv, umv, a5);
+            d[0] = d0;
+            d[1] = fmaR(R(1.0 / 3.0), ux, dx);
+            d[3] = fmaR(R(-1.0 / 3.0), ux, dx);
+            d[2] = fmaR(R(1.0 / 3.0), uy, dy);
+            d[4] = fmaR(R(-1.0 / 3.0), uy, dy);
+            d[5] = fmaR(R(1.0 / 12.0), upv, dp);
+            d[7] = fmaR(R(-1.0 / 12.0), upv, dp);
+            d[8] = fmaR(R(1.0 / 12.0), umv, dm);
+            d[6] = fmaR(R(-1.0 / 12.0), umv, dm);
+            R a = R(0), b = R(0), c = R(0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                w[i] = rcpR(d[i]);
+                const R wh = dh[i] * w[i];
+                a = fmaR(ds[i], wh, a);
+                b = fmaR(dh[i], wh, b);
+                c = fmaR(ds[i] * w[i], ds[i], c);
+            }
+            ratio = divR(a, b);
+            bsum = b;
+            const R gs = fmaR(-K.two_m_inv_beta, ratio, K.inv_beta);
+            active = !(b <= K.guard * c);
+            gam = active ? gs : R(2);
+        }
+
+        // --------------------------------------------------------- reverse
+        // g'_i = g_i - 2 beta ds_i - beta gamma dh_i
+        R dsb[9], dhb[9];
+        R gamb = R(0), db = R(0);
+        const R tb = R(2) * K.beta, bg = K.beta * gam;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            lam[i] = mu[i];
+            dsb[i] = -tb * mu[i];
+            dhb[i] = -bg * mu[i];
+            gamb = fmaR(mu[i], dh[i], gamb);
+            db = fmaR(mu[i], fmaR(gam, dh[i], R(2) * ds[i]), db);
+        }
+        gamb = -K.beta * gamb;
+        dbeta = -db;
+        if constexpr (GM != GFIX && !FROZEN) {
+            if (active) {
+                // gamma = 1/beta - (2 - 1/beta) a / b
+                const R ib2 = K.inv_beta * K.inv_beta;
+                dbeta = fmaR(gamb, -(R(1) + ratio) * ib2, dbeta);
+                const R rb = -K.two_m_inv_beta * gamb;     // adjoint of a / b
+                const R ab = rb / bsum;                    // adjoint of a
+                const R bb = -rb * ratio / bsum;           // adjoint of b
+                R uxw = R(0), uyw = R(0);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    // a = sum ds dh w, b = sum dh dh w (c enters the guard only)
+                    dsb[i] = fmaR(ab * dh[i], w[i], dsb[i]);
+                    dhb[i] = fmaR(fmaR(ab, ds[i], R(2) * bb * dh[i]), w[i], dhb[i]);
+                    const R wb = dh[i] * fmaR(ab, ds[i], bb * dh[i]);
+                    const R dbar = -wb * w[i] * w[i];       // adjoint of d_i
+                    // d_i = W_i (1 - 1.5 |u|^2 + 4.5 (c.u)^2 + 3 c.u)
+                    const R cu = R(kCx[i]) * ux + R(kCy[i]) * uy;
+                    const R wd = R(weight(i)) * dbar;
+                    uxw = fmaR(wd, fmaR(R(9) * cu, R(kCx[i]), fmaR(R(-3), ux, R(3) * R(kCx[i]))), uxw);
+                    uyw = fmaR(wd, fmaR(R(9) * cu, R(kCy[i]), fmaR(R(-3), uy, R(3) * R(kCy[i]))), uyw);
+                }
+                uxb += uxw;
+                uyb += uyw;
+            }
+        }
+        // ds = P(Ts, dN, dP, Qxs, Qys, As), dh = P(dT - Ts, 0, 0, dQx - Qxs, dQy - Qys, dA - As)
+        R sTb, sNb, sPb, sQxb, sQyb, sAb, hTb, hNb, hPb, hQxb, hQyb, hAb;
+        pop_to_moments_adj<R>(dsb, sTb, sNb, sPb, sQxb, sQyb, sAb);
+        pop_to_moments_adj<R>(dhb, hTb, hNb, hPb, hQxb, hQyb, hAb);
+        R dTb = hTb, dNb = sNb, dPb = sPb, dQxb = hQxb, dQyb = hQyb, dAb = hAb;
+        const R Tsb = sTb - hTb, Qxsb = sQxb - hQxb, Qysb = sQyb - hQyb, Asb = sAb - hAb;
+        if constexpr (VAR == VC) {
+            dTb += Tsb;
+        } else if constexpr (VAR == VA || VAR == VB) {
+            if constexpr (VAR == VA) dTb += Tsb + R(0.5) * (ux * Qxsb + uy * Qysb + u2 * Asb);
+            dNb += R(0.5) * (uy * Qysb - ux * Qxsb - (uxx - uyy) * Asb);
+            dPb += R(2) * (uy * Qxsb + ux * Qysb) + R(4) * ux * uy * Asb;
+            uxb += R(0.5) * (tT - dN) * Qxsb + R(2) * dP * Qysb + (R(4) * uy * dP + ux * (tT - dN)) * Asb;
+            uyb += R(2) * dP * Qxsb + R(0.5) * (tT + dN) * Qysb + (R(4) * ux * dP + uy * (tT + dN)) * Asb;
+        }
+        // dT = dPxx + dPyy, dN = dPxx - dPyy, dP = dPxy
+        const R dPxxb = dTb + dNb, dPyyb = dTb - dNb, dPxyb = dPb;
+        // moments of g - feq
+        Sxxb = dPxxb;
+        Syyb = dPyyb;
+        Sxyb = dPxyb;
+        Qxrb = dQxb;
+        Qyrb = dQyb;
+        Arb = dAb;
+        drb += -(dPxxb + dPyyb) * third - dAb * ninth;
+        jxb += -dPxxb * ux - dPxyb * uy - dQxb * third - dAb * ux * third;
+        jyb += -dPyyb * uy - dQyb * third - dAb * uy * third;
+        uxb += -dPxxb * jx - dAb * jx * third;
+        uyb += -dPyyb * jy - dPxyb * jx - dAb * jy * third;
+    }
+    // u = j / rho, rho = rho0 + dr
+    jxb = fmaR(uxb, ir, jxb);
+    jyb = fmaR(uyb, ir, jyb);
+    drb -= (uxb * ux + uyb * uy) * ir;
+    // dr = sum g, j = sum c g, and the raw sums of g
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R cx = R(kCx[i]), cy = R(kCy[i]);
+        R s = drb + cx * jxb + cy * jyb;
+        if constexpr (COLL != LBGK) {
+            s += cx * cx * Sxxb + cy * cy * Syyb + cx * cy * Sxyb + cx * cy * cy * Qxrb +
+                 cx * cx * cy * Qyrb + cx * cx * cy * cy * Arb;
+        }
+        lam[i] += s;
+    }
+}
+
+}  // namespace kbc

@@ -23,6 +23,8 @@ struct lbm_ctx {
     kbc::StepShape shape;
     double* dscratch;       // ux, uy, omega fields + diagnostics partials
     size_t dscratch_elems;
+    double* ascratch;       // adjoint: block partials + initial-state stencil fields
+    size_t ascratch_elems;
 };
 
 namespace {
@@ -100,6 +102,7 @@ kbc::Lattice lattice_of(const lbm_params& p, size_t pitch) {
     L.guard = p.gamma_guard;
     L.gamma_fixed = p.gamma_fixed;
     L.stream = static_cast<hipStream_t>(p.stream);
+    L.adj_frozen = 0;
     return L;
 }
 
@@ -150,6 +153,8 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     c->shape = default_shape(p->form);
     c->dscratch = nullptr;
     c->dscratch_elems = 0;
+    c->ascratch = nullptr;
+    c->ascratch_elems = 0;
     rc = kbc::launch_init(c->L, buf_a, rho, ux, uy, grad, mode);
     if (rc) {
         delete c;
@@ -279,13 +284,84 @@ int lbm_set_beta(lbm_ctx* c, double beta) {
 int lbm_free(lbm_ctx* c) {
     if (!c) return LBM_OK;
     int rc = LBM_OK;
-    if (c->dscratch) {
+    if (c->dscratch || c->ascratch) {
         hipError_t e = hipStreamSynchronize(c->L.stream);
         if (e != hipSuccess) rc = hip_fail(e, "lbm_free sync");
-        (void)hipFree(c->dscratch);
+        if (c->dscratch) (void)hipFree(c->dscratch);
+        if (c->ascratch) (void)hipFree(c->ascratch);
     }
     delete c;
     return rc;
+}
+
+size_t lbm_adjoint_bytes(int32_t nx, int32_t ny, int32_t form) {
+    const size_t pitch = lbm_required_pitch(nx, form);
+    if (pitch == 0 || ny < 1) return 0;
+    return 9 * static_cast<size_t>(ny) * pitch * (form == LBM_F64 ? 8 : 4);
+}
+
+int lbm_step_buffers(lbm_ctx* c, const void* src, void* dst) {
+    if (!c || !src || !dst || src == dst) return fail(LBM_EINVAL, "invalid ctx or buffers");
+    return launch_result(kbc::launch_step(c->L, src, dst, c->shape), "lbm_step_buffers");
+}
+
+namespace {
+int ensure_ascratch(lbm_ctx* c, size_t need) {
+    if (c->ascratch_elems >= need) return LBM_OK;
+    if (c->ascratch) {
+        hipError_t e = hipStreamSynchronize(c->L.stream);
+        if (e != hipSuccess) return hip_fail(e, "adjoint scratch sync");
+        (void)hipFree(c->ascratch);
+        c->ascratch = nullptr;
+        c->ascratch_elems = 0;
+    }
+    hipError_t e = hipMalloc(&c->ascratch, need * sizeof(double));
+    if (e != hipSuccess) {
+        c->ascratch = nullptr;
+        return fail(LBM_ENOMEM, "adjoint scratch: %s", hipGetErrorString(e));
+    }
+    c->ascratch_elems = need;
+    return LBM_OK;
+}
+}  // namespace
+
+int lbm_set_adjoint_gamma(lbm_ctx* c, int32_t mode) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (mode != LBM_ADJ_GAMMA_FULL && mode != LBM_ADJ_GAMMA_FROZEN) return fail(LBM_EINVAL, "unknown adjoint gamma mode %d", mode);
+    c->L.adj_frozen = (mode == LBM_ADJ_GAMMA_FROZEN) ? 1 : 0;
+    return LBM_OK;
+}
+
+int lbm_adjoint_seed(lbm_ctx* c, const void* state, const double* dL_drho, const double* dL_dux,
+                     const double* dL_duy, void* lam) {
+    if (!c || !state || !lam) return fail(LBM_EINVAL, "ctx, state and lam must not be NULL");
+    return launch_result(kbc::launch_adjoint_seed(c->L, state, dL_drho, dL_dux, dL_duy, lam), "lbm_adjoint_seed");
+}
+
+int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta) {
+    if (!c || !state || !lam_in || !lam_out || lam_in == lam_out)
+        return fail(LBM_EINVAL, "ctx, state and two distinct adjoint buffers are required");
+    const int64_t nb = kbc::adjoint_step_blocks(c->L);
+    int rc = ensure_ascratch(c, static_cast<size_t>(nb));
+    if (rc) return rc;
+    return launch_result(kbc::launch_adjoint_step(c->L, state, lam_in, lam_out, c->ascratch, nb, dbeta),
+                         "lbm_adjoint_step");
+}
+
+int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, int32_t mode,
+                     const void* lam0, double* grad_ux, double* grad_uy, double* dbeta) {
+    if (!c || !ux || !uy || !lam0 || !grad_ux || !grad_uy)
+        return fail(LBM_EINVAL, "ctx, ux, uy, lam0 and both gradient outputs are required");
+    if (mode != LBM_INIT_EQ && mode != LBM_INIT_GRAD_CD)
+        return fail(LBM_EUNSUPPORTED, "adjoint of init mode %d is not built", mode);
+    const size_t N = static_cast<size_t>(c->p.nx) * c->p.ny;
+    const size_t nb = (N + 255) / 256;
+    int rc = ensure_ascratch(c, nb + 4 * N);
+    if (rc) return rc;
+    return launch_result(kbc::launch_adjoint_init(c->L, rho, ux, uy, mode == LBM_INIT_GRAD_CD ? 1 : 0, lam0,
+                                                  grad_ux, grad_uy, c->ascratch + nb, c->ascratch,
+                                                  static_cast<int64_t>(nb), dbeta),
+                         "lbm_adjoint_init");
 }
 
 int lbm_copy_probe(void* dst, const void* src, size_t n_words, void* stream) {

@@ -15,6 +15,7 @@ struct Lattice {
     int form, collision, variant, gamma_mode;
     double beta, rho0, guard, gamma_fixed;
     hipStream_t stream;
+    int adj_frozen;         // adjoint holds gamma at its forward value
 };
 
 // step kernel tile: `width` in {64, 128, 256} nodes, each thread walks `rpt`
@@ -42,6 +43,17 @@ int launch_diag(const Lattice& L, const void* src, double* ux_s, double* uy_s, d
                 double* partials);
 
 int launch_copy(void* dst, const void* src, size_t n_words, hipStream_t stream);
+
+// adjoint (kbc_adjoint.hip); partials: scratch of at least nblocks_cap doubles;
+// acc (nullable): a device double that receives += the beta derivative
+int64_t adjoint_step_blocks(const Lattice& L);
+int launch_adjoint_seed(const Lattice& L, const void* state, const double* drho, const double* dux,
+                        const double* duy, void* lam);
+int launch_adjoint_step(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
+                        int64_t nblocks_cap, double* acc);
+int launch_adjoint_init(const Lattice& L, const double* rho, const double* ux, const double* uy, int mode,
+                        const void* lam0, double* gux, double* guy, double* P, double* partials,
+                        int64_t nblocks_cap, double* acc);
 
 // kernel-name lookup for profiling output
 const char* step_kernel_name(const Lattice& L);

@@ -126,6 +126,37 @@ class Sim:
         L.check(self.lib.lbm_diagnostics(self.ctx, ctypes.byref(d)), "lbm_diagnostics")
         return {k: getattr(d, k) for k in L.DIAG_FIELDS if k != "reserved"}
 
+    # ------------------------------------------------------------- adjoint
+    @property
+    def adjoint_dtype(self):
+        return torch.float64 if self.form == L.F64 else torch.float32
+
+    def set_adjoint_gamma(self, frozen: bool):
+        L.check(self.lib.lbm_set_adjoint_gamma(self.ctx, 1 if frozen else 0), "lbm_set_adjoint_gamma")
+
+    def new_adjoint(self) -> torch.Tensor:
+        return torch.empty((9, self.ny, self.pitch), dtype=self.adjoint_dtype, device=self.device)
+
+    def new_state(self) -> torch.Tensor:
+        return torch.empty_like(self.buf_a)
+
+    def step_buffers(self, src: torch.Tensor, dst: torch.Tensor):
+        L.check(self.lib.lbm_step_buffers(self.ctx, L.ptr(src), L.ptr(dst)), "lbm_step_buffers")
+
+    def adjoint_seed(self, state, lam, drho=None, dux=None, duy=None):
+        drho, dux, duy = (None if a is None else _dev64(a, self.device) for a in (drho, dux, duy))
+        L.check(self.lib.lbm_adjoint_seed(self.ctx, L.ptr(state), L.ptr(drho), L.ptr(dux), L.ptr(duy),
+                                          L.ptr(lam)), "lbm_adjoint_seed")
+        self._inputs = (drho, dux, duy)
+
+    def adjoint_step(self, state, lam_in, lam_out, dbeta=None):
+        L.check(self.lib.lbm_adjoint_step(self.ctx, L.ptr(state), L.ptr(lam_in), L.ptr(lam_out), L.ptr(dbeta)),
+                "lbm_adjoint_step")
+
+    def adjoint_init(self, ux0, uy0, lam0, grad_ux, grad_uy, dbeta=None, rho=None, mode: str = "grad_cd"):
+        L.check(self.lib.lbm_adjoint_init(self.ctx, L.ptr(rho), L.ptr(ux0), L.ptr(uy0), _INIT[mode], L.ptr(lam0),
+                                          L.ptr(grad_ux), L.ptr(grad_uy), L.ptr(dbeta)), "lbm_adjoint_init")
+
     def state_buffer(self) -> torch.Tensor:
         p = self.lib.lbm_state_buffer(self.ctx)
         return self.buf_a if p == self.buf_a.data_ptr() else self.buf_b
