@@ -217,6 +217,36 @@ int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* la
 int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, int32_t mode,
                      const void* lam0, double* grad_ux, double* grad_uy, double* dbeta);
 
+/* ----------------------------------------------------------------- ensemble
+ * Many independent lattices (e.g. of different sizes and beta) advanced
+ * together.  An ensemble borrows member contexts created with lbm_init (same
+ * form, collision, variant, stabiliser mode and stream; planes below 4 GiB)
+ * and steps all of them; each member keeps its own buffers, parameters and
+ * entry points (moments, populations, diagnostics).  Stepping is bitwise
+ * identical to calling lbm_step on every member. */
+typedef struct lbm_ens lbm_ens;
+
+int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count);
+
+/* Tile of the ensemble kernel: 128 x 4 (width 128, 2 rows per thread),
+ * 256 x 1 or 256 x 2; flags as for lbm_set_tile.  Synchronises the stream. */
+int lbm_ensemble_set_tile(lbm_ens* e, int32_t width, int32_t rows_per_thread, int32_t flags);
+
+/* Advance every member nsteps: persistent = 0 launches once per step over all
+ * members' tiles.  persistent = 1 (one cooperative launch of resident
+ * workgroups looping over the steps with a grid-wide barrier in between) is
+ * built but switched off and returns LBM_EUNSUPPORTED: its first run on the
+ * GPU did not finish and the cause has not been shown.  All members must hold
+ * their current state in the same buffer index (true when they have been
+ * stepped equally since lbm_init). */
+int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent);
+
+/* Workgroups of the persistent launch (resident capacity, a multiple of 8). */
+int lbm_ensemble_blocks(const lbm_ens* e);
+
+/* Release the ensemble (never the members).  Synchronises the stream. */
+int lbm_ensemble_free(lbm_ens* e);
+
 /* Streaming copy dst[i] = src[i] of n 4-byte words on `stream`: the bandwidth
  * reference measured beside the step. */
 int lbm_copy_probe(void* dst, const void* src, size_t n_words, void* stream);

@@ -67,6 +67,11 @@ _SIGS = {
     "lbm_free": (_c.c_int, [_vp]),
     "lbm_last_error": (_c.c_char_p, []),
     "lbm_copy_probe": (_c.c_int, [_vp, _vp, _c.c_size_t, _vp]),
+    "lbm_ensemble_create": (_c.c_int, [_c.POINTER(_vp), _c.POINTER(_vp), _c.c_int32]),
+    "lbm_ensemble_set_tile": (_c.c_int, [_vp, _c.c_int32, _c.c_int32, _c.c_int32]),
+    "lbm_ensemble_step": (_c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    "lbm_ensemble_blocks": (_c.c_int, [_vp]),
+    "lbm_ensemble_free": (_c.c_int, [_vp]),
     "lbm_set_adjoint_gamma": (_c.c_int, [_vp, _c.c_int32]),
     "lbm_adjoint_bytes": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),
     "lbm_step_buffers": (_c.c_int, [_vp, _vp, _vp]),

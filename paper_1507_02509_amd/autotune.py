@@ -1,0 +1,131 @@
+"""Tile-shape autotuner for the step and ensemble kernels.
+
+It times every candidate tile (width, rows per thread, non-temporal stores)
+on the caller's own lattice or ensemble with HIP events, keeps the one with
+the smallest median time, and caches the choice in a JSON file keyed by the
+device name and the configuration (form, collision, variant, lattice sizes).
+The lattice state is restored afterwards: every trial takes an even number of
+steps and the state buffers are copied back, so tuning changes nothing but
+the tile.  Results of the step kernels are bitwise identical for every tile,
+so the choice only affects speed.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import torch
+
+STEP_TILES = [(w, r, nt) for (w, r) in ((64, 1), (64, 4), (128, 1), (128, 2), (128, 4), (256, 1), (256, 2))
+              for nt in (False, True)]
+ENSEMBLE_TILES = [(w, r, nt) for (w, r) in ((128, 2), (256, 1), (256, 2)) for nt in (False, True)]
+
+
+def cache_path() -> str:
+    return os.environ.get("KBC_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_1507_02509_amd", "autotune.json"))
+
+
+def _load(path):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _time(run, steps: int, reps: int) -> float:
+    """Median milliseconds per step of run(steps) over reps repetitions."""
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / steps)
+    times.sort()
+    return times[len(times) // 2]
+
+
+def _sim_key(sim) -> str:
+    return "|".join(["sim", torch.cuda.get_device_name(sim.device), str(sim.form), str(sim.params.collision),
+                     str(sim.params.variant), f"{sim.nx}x{sim.ny}"])
+
+
+def tune_sim(sim, steps: int = 10, reps: int = 3, candidates=None, use_cache: bool = True):
+    """Choose and apply the fastest step tile for this lattice; returns
+    (width, rows_per_thread, nontemporal) and the per-candidate timings."""
+    path = cache_path()
+    key = _sim_key(sim)
+    cache = _load(path) if use_cache else {}
+    if use_cache and key in cache:
+        best = tuple(cache[key]["tile"])
+        sim.set_tile(*best)
+        return best, cache[key].get("ms", {})
+    steps += steps % 2
+    snap = sim.state_buffer().clone()
+    n0 = sim.steps
+    timings = {}
+    for cand in candidates or STEP_TILES:
+        sim.set_tile(*cand)
+        sim.step(2)
+        timings[cand] = _time(sim.step, steps, reps)
+    best = min(timings, key=timings.get)
+    sim.set_tile(*best)
+    sim.state_buffer().copy_(snap)
+    sim.lib.lbm_set_step(sim.ctx, n0)
+    torch.cuda.synchronize()
+    if use_cache:
+        cache = _load(path)
+        cache[key] = {"tile": list(best), "ms": {str(list(k)): v for k, v in timings.items()}}
+        _store(path, cache)
+    return best, timings
+
+
+def _ens_key(ens) -> str:
+    m0 = ens.members[0]
+    sizes = hashlib.sha1(",".join(f"{m.nx}x{m.ny}" for m in ens.members).encode()).hexdigest()[:12]
+    return "|".join(["ensemble", torch.cuda.get_device_name(m0.device), str(m0.form), str(m0.params.collision),
+                     str(m0.params.variant), str(len(ens.members)), sizes])
+
+
+def tune_ensemble(ens, steps: int = 10, reps: int = 3, persistent: bool = False, candidates=None,
+                  use_cache: bool = True):
+    """Choose and apply the fastest ensemble tile; returns the tile and timings."""
+    path = cache_path()
+    key = _ens_key(ens) + f"|{'persistent' if persistent else 'per-step'}"
+    cache = _load(path) if use_cache else {}
+    if use_cache and key in cache:
+        best = tuple(cache[key]["tile"])
+        ens.set_tile(*best)
+        return best, cache[key].get("ms", {})
+    steps += steps % 2
+    snaps = [m.state_buffer().clone() for m in ens.members]
+    n0 = [m.steps for m in ens.members]
+    timings = {}
+    for cand in candidates or ENSEMBLE_TILES:
+        ens.set_tile(*cand)
+        ens.step(2, persistent)
+        timings[cand] = _time(lambda k: ens.step(k, persistent), steps, reps)
+    best = min(timings, key=timings.get)
+    ens.set_tile(*best)
+    for m, snap, n in zip(ens.members, snaps, n0):
+        m.state_buffer().copy_(snap)
+        m.lib.lbm_set_step(m.ctx, n)
+    torch.cuda.synchronize()
+    if use_cache:
+        cache = _load(path)
+        cache[key] = {"tile": list(best), "ms": {str(list(k)): v for k, v in timings.items()}}
+        _store(path, cache)
+    return best, timings

@@ -364,6 +364,162 @@ int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const doub
                          "lbm_adjoint_init");
 }
 
+// ------------------------------------------------------------------ ensemble
+struct lbm_ens {
+    std::vector<lbm_ctx*> m;
+    kbc::Lattice L;             // common form, collision, variant, stabiliser, stream
+    kbc::StepShape shape;
+    kbc::EnsEntry* dtab;
+    int ntiles;
+    int blocks;                 // resident workgroups for the persistent launch
+};
+
+namespace {
+
+bool ens_shape_ok(const kbc::StepShape& s) {
+    return ((s.width == 128 && s.rpt == 2) || (s.width == 256 && (s.rpt == 1 || s.rpt == 2))) &&
+           (s.nt == 0 || s.nt == 1);
+}
+
+int ens_build(lbm_ens* e) {
+    std::vector<kbc::EnsEntry> tab(e->m.size());
+    int64_t tiles = 0;
+    const int tw = e->shape.width, th = (256 / e->shape.width) * e->shape.rpt;
+    for (size_t r = 0; r < e->m.size(); ++r) {
+        const lbm_ctx* c = e->m[r];
+        kbc::EnsEntry& t = tab[r];
+        t.buf[0] = c->buf[0];
+        t.buf[1] = c->buf[1];
+        t.nx = c->p.nx;
+        t.ny = c->p.ny;
+        t.ntx = (c->p.nx + tw - 1) / tw;
+        t.pitch = c->L.pitch;
+        t.tile_start = static_cast<int32_t>(tiles);
+        tiles += static_cast<int64_t>(t.ntx) * ((c->p.ny + th - 1) / th);
+        if (tiles > (int64_t{1} << 30)) return fail(LBM_EINVAL, "ensemble has too many tiles");
+        t.beta = c->L.beta;
+        t.inv_beta = 1.0 / c->L.beta;
+        t.two_m_inv_beta = 2.0 - 1.0 / c->L.beta;
+        t.rho0 = c->L.rho0;
+        t.guard = c->L.guard;
+        t.gamma_fixed = c->L.gamma_fixed;
+    }
+    if (!e->dtab) {
+        hipError_t err = hipMalloc(&e->dtab, tab.size() * sizeof(kbc::EnsEntry));
+        if (err != hipSuccess) {
+            e->dtab = nullptr;
+            return fail(LBM_ENOMEM, "ensemble table: %s", hipGetErrorString(err));
+        }
+    }
+    hipError_t err = hipStreamSynchronize(e->L.stream);
+    if (err == hipSuccess)
+        err = hipMemcpy(e->dtab, tab.data(), tab.size() * sizeof(kbc::EnsEntry), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return hip_fail(err, "ensemble table upload");
+    e->ntiles = static_cast<int>(tiles);
+    kbc::EnsLaunch a{};
+    a.shape = e->shape;
+    a.query_blocks = &e->blocks;
+    return launch_result(kbc::launch_ensemble(e->L, a), "ensemble occupancy");
+}
+
+}  // namespace
+
+int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!members || count < 1) return fail(LBM_EINVAL, "need at least one member");
+    const lbm_ctx* m0 = members[0];
+    for (int32_t r = 0; r < count; ++r) {
+        const lbm_ctx* c = members[r];
+        if (!c) return fail(LBM_EINVAL, "member %d is NULL", r);
+        if (c->p.form != m0->p.form || c->p.collision != m0->p.collision ||
+            (c->p.collision == LBM_KBC && c->p.variant != m0->p.variant) || c->p.gamma_mode != m0->p.gamma_mode ||
+            c->p.stream != m0->p.stream)
+            return fail(LBM_EINVAL, "member %d differs in form, collision, variant, stabiliser or stream", r);
+        if (c->p.gamma_mode == LBM_GAMMA_EXACT) return fail(LBM_EUNSUPPORTED, "exact stabiliser in an ensemble");
+        const uint64_t plane = static_cast<uint64_t>(c->p.ny) * static_cast<uint64_t>(c->L.pitch) *
+                               static_cast<uint64_t>(form_bytes(c->p.form));
+        if (plane > (uint64_t{1} << 32)) return fail(LBM_EUNSUPPORTED, "member %d: plane above 4 GiB", r);
+        for (int32_t q = 0; q < r; ++q)
+            if (members[q] == c) return fail(LBM_EINVAL, "member %d repeats member %d", r, q);
+    }
+    lbm_ens* e = new (std::nothrow) lbm_ens();
+    if (!e) return fail(LBM_ENOMEM, "ensemble allocation failed");
+    e->m.assign(members, members + count);
+    e->L = m0->L;
+    e->shape = default_shape(m0->p.form);
+    if (!ens_shape_ok(e->shape)) {
+        e->shape.width = 128;
+        e->shape.rpt = 2;
+    }
+    e->dtab = nullptr;
+    e->blocks = 0;
+    int rc = ens_build(e);
+    if (rc) {
+        if (e->dtab) (void)hipFree(e->dtab);
+        delete e;
+        return rc;
+    }
+    *out = e;
+    return LBM_OK;
+}
+
+int lbm_ensemble_set_tile(lbm_ens* e, int32_t width, int32_t rows_per_thread, int32_t flags) {
+    if (!e) return fail(LBM_EINVAL, "ensemble is NULL");
+    kbc::StepShape s;
+    s.width = width;
+    s.rpt = rows_per_thread;
+    s.nt = (flags & LBM_TILE_NONTEMPORAL) ? 1 : 0;
+    if ((flags & ~LBM_TILE_NONTEMPORAL) != 0 || !ens_shape_ok(s))
+        return fail(LBM_EINVAL, "ensemble tiles: 128 x 4, 256 x 1 or 256 x 2");
+    e->shape = s;
+    return ens_build(e);
+}
+
+int lbm_ensemble_blocks(const lbm_ens* e) { return e ? e->blocks : -1; }
+
+int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent) {
+    if (!e) return fail(LBM_EINVAL, "ensemble is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (persistent)
+        return fail(LBM_EUNSUPPORTED,
+                    "the persistent (cooperative, grid-barrier) ensemble launch is switched off: its first GPU run "
+                    "did not finish and no cause has been shown; use persistent = 0 (one launch per step)");
+    if (nsteps == 0) return LBM_OK;
+    const int cur = e->m[0]->cur;
+    for (size_t r = 1; r < e->m.size(); ++r)
+        if (e->m[r]->cur != cur) return fail(LBM_EINVAL, "members hold their states in different buffers");
+    kbc::EnsLaunch a{};
+    a.table = e->dtab;
+    a.nmem = static_cast<int>(e->m.size());
+    a.ntiles = e->ntiles;
+    a.nsteps = nsteps;
+    a.parity = cur;
+    a.persistent = persistent != 0;
+    a.blocks = e->blocks;
+    a.shape = e->shape;
+    a.stream = e->L.stream;
+    const int rc = kbc::launch_ensemble(e->L, a);
+    if (rc) return launch_result(rc, "lbm_ensemble_step");
+    for (lbm_ctx* c : e->m) {
+        c->cur ^= (nsteps & 1);
+        c->steps += nsteps;
+    }
+    return LBM_OK;
+}
+
+int lbm_ensemble_free(lbm_ens* e) {
+    if (!e) return LBM_OK;
+    int rc = LBM_OK;
+    if (e->dtab) {
+        hipError_t err = hipStreamSynchronize(e->L.stream);
+        if (err != hipSuccess) rc = hip_fail(err, "lbm_ensemble_free sync");
+        (void)hipFree(e->dtab);
+    }
+    delete e;
+    return rc;
+}
+
 int lbm_copy_probe(void* dst, const void* src, size_t n_words, void* stream) {
     if (!dst || !src) return fail(LBM_EINVAL, "dst and src must not be NULL");
     return launch_result(kbc::launch_copy(dst, src, n_words, static_cast<hipStream_t>(stream)), "lbm_copy_probe");

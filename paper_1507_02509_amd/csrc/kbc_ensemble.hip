@@ -1,0 +1,123 @@
+// kbc_ensemble.hip -- many independent lattices of different sizes advanced by
+// one kernel.
+//
+// A device table lists the members (buffers, size, pitch, beta) and the first
+// index of each member's tiles in one global tile numbering (members in order,
+// row-major tiles within a member).  The tile range is cut into eight equal
+// contiguous bands, one per XCD (workgroup b runs on XCD b % 8), and the
+// workgroups of an XCD deal its band out round-robin, so x-neighbour tiles of
+// one member meet in the same L2 as in the single-lattice step.
+//
+// The same kernel runs in two modes:
+//   * one launch per step (nsteps = 1): one workgroup per tile;
+//   * one persistent cooperative launch for many steps: as many workgroups as
+//     can be resident, looping over their tiles each step, with a grid-wide
+//     barrier between steps (cooperative groups; the barrier's device-scope
+//     fences make the new states of every XCD visible to all others).
+// Both modes run the per-node code of the single-lattice step on the same
+// tiles, so results are bitwise identical to stepping each member alone.
+#include <hip/hip_cooperative_groups.h>
+
+#include "kbc_launch.hpp"
+#include "kbc_tile.hpp"
+
+namespace kbc {
+
+namespace {
+
+template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
+__global__ __launch_bounds__(256) void k_ens(const EnsEntry* __restrict__ tab, int nmem, int ntiles,
+                                             int nsteps, int parity) {
+    using F = Form<FORM>;
+    using S = typename F::S;
+    using R = typename F::R;
+    const int xcd = static_cast<int>(blockIdx.x & 7u), j = static_cast<int>(blockIdx.x >> 3);
+    const int m = static_cast<int>(gridDim.x >> 3);
+    const int band = (ntiles + 7) >> 3;
+    const int start = xcd * band;
+    const int end = (start + band < ntiles) ? start + band : ntiles;
+    for (int s = 0; s < nsteps; ++s) {
+        const int par = (parity + s) & 1;
+        for (int t = start + j; t < end; t += m) {
+            // member holding tile t: the last entry with tile_start <= t
+            int lo = 0, hi = nmem - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (tab[mid].tile_start <= t) lo = mid; else hi = mid - 1;
+            }
+            const EnsEntry& e = tab[lo];
+            Coef<R> K;
+            K.beta = static_cast<R>(e.beta);
+            K.inv_beta = static_cast<R>(e.inv_beta);
+            K.two_m_inv_beta = static_cast<R>(e.two_m_inv_beta);
+            K.rho0 = static_cast<R>(e.rho0);
+            K.guard = static_cast<R>(e.guard);
+            K.gamma_fixed = static_cast<R>(e.gamma_fixed);
+            const int lt = t - e.tile_start;
+            step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT, false>(
+                static_cast<const S*>(e.buf[par]), static_cast<S*>(e.buf[par ^ 1]), e.nx, e.ny, e.pitch,
+                lt % e.ntx, lt / e.ntx, K);
+        }
+        if (s + 1 < nsteps) cooperative_groups::this_grid().sync();
+    }
+}
+
+template <int FORM, int COLL, int VAR, int GM>
+struct EnsOp {
+    template <int TXW, int RPT, bool NT>
+    static int go(const EnsLaunch& a) {
+        auto kern = k_ens<FORM, COLL, VAR, GM, TXW, RPT, NT>;
+        if (a.query_blocks) {
+            int per_cu = 0, dev = 0, cus = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return -2;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -2;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 256, 0) !=
+                hipSuccess)
+                return -2;
+            *a.query_blocks = (per_cu * cus) / 8 * 8;
+            return 0;
+        }
+        const EnsEntry* tab = a.table;
+        int nmem = a.nmem, ntiles = a.ntiles, nsteps = a.nsteps, parity = a.parity;
+        if (!a.persistent) {
+            const int band = (ntiles + 7) / 8;
+            for (int s = 0; s < nsteps; ++s) {
+                const int one = 1, par = (parity + s) & 1;
+                kern<<<dim3(8u * static_cast<unsigned>(band)), dim3(256), 0, a.stream>>>(tab, nmem, ntiles, one, par);
+                if (hipGetLastError() != hipSuccess) return -2;
+            }
+            return 0;
+        }
+        if (a.blocks < 8 || a.blocks % 8) return -1;
+        void* args[] = {&tab, &nmem, &ntiles, &nsteps, &parity};
+        if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(static_cast<unsigned>(a.blocks)),
+                                       dim3(256), args, 0, a.stream) != hipSuccess)
+            return -2;
+        return 0;
+    }
+    static int run(const Lattice& L, const EnsLaunch& a) {
+        (void)L;
+        const StepShape& sh = a.shape;
+        const int key = sh.width * 16 + sh.rpt;
+        if (sh.nt) {
+            switch (key) {
+                case 128 * 16 + 2: return go<2, 2, true>(a);
+                case 256 * 16 + 1: return go<4, 1, true>(a);
+                case 256 * 16 + 2: return go<4, 2, true>(a);
+                default: return -5;
+            }
+        }
+        switch (key) {
+            case 128 * 16 + 2: return go<2, 2, false>(a);
+            case 256 * 16 + 1: return go<4, 1, false>(a);
+            case 256 * 16 + 2: return go<4, 2, false>(a);
+            default: return -5;
+        }
+    }
+};
+
+}  // namespace
+
+int launch_ensemble(const Lattice& L, const EnsLaunch& a) { return dispatch<EnsOp>(L, a); }
+
+}  // namespace kbc

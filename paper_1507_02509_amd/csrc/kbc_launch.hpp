@@ -44,6 +44,26 @@ int launch_diag(const Lattice& L, const void* src, double* ux_s, double* uy_s, d
 
 int launch_copy(void* dst, const void* src, size_t n_words, hipStream_t stream);
 
+// ensemble (kbc_ensemble.hip): one table entry per member lattice
+struct EnsEntry {
+    void* buf[2];           // the member's two population buffers
+    int32_t nx, ny;
+    int32_t ntx;            // tiles per row for the ensemble's tile shape
+    int32_t tile_start;     // first global tile index of this member
+    int64_t pitch;
+    double beta, inv_beta, two_m_inv_beta, rho0, guard, gamma_fixed;
+};
+struct EnsLaunch {
+    const EnsEntry* table;  // device copy of the member table
+    int nmem, ntiles, nsteps, parity;
+    bool persistent;        // one cooperative launch for all nsteps
+    int blocks;             // persistent grid size (multiple of 8)
+    StepShape shape;        // (128,2), (256,1) or (256,2), with or without nt
+    hipStream_t stream;
+    int* query_blocks;      // if set: only report the resident-workgroup count
+};
+int launch_ensemble(const Lattice& L, const EnsLaunch& a);
+
 // adjoint (kbc_adjoint.hip); partials: scratch of at least nblocks_cap doubles;
 // acc (nullable): a device double that receives += the beta derivative
 int64_t adjoint_step_blocks(const Lattice& L);

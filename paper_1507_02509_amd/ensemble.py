@@ -1,0 +1,65 @@
+"""Ensembles of independent lattices of different sizes advanced by one kernel
+(include/kbc.h, "ensemble").  Members are ordinary Sim objects; the ensemble
+only steps them."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+from . import inputs
+from .sim import Sim, beta_from_nu
+
+
+class Ensemble:
+    def __init__(self, members: list[Sim]):
+        if not members:
+            raise ValueError("empty ensemble")
+        self.lib = L.load()
+        self.members = list(members)
+        arr = (ctypes.c_void_p * len(members))(*[m.ctx.value for m in members])
+        self.h = ctypes.c_void_p()
+        L.check(self.lib.lbm_ensemble_create(ctypes.byref(self.h), arr, len(members)), "lbm_ensemble_create")
+
+    @property
+    def nodes(self) -> int:
+        return sum(m.nx * m.ny for m in self.members)
+
+    @property
+    def blocks(self) -> int:
+        return int(self.lib.lbm_ensemble_blocks(self.h))
+
+    def set_tile(self, width: int, rows_per_thread: int, nontemporal: bool = False):
+        L.check(self.lib.lbm_ensemble_set_tile(self.h, int(width), int(rows_per_thread), 1 if nontemporal else 0),
+                "lbm_ensemble_set_tile")
+
+    def step(self, n: int = 1, persistent: bool = False) -> "Ensemble":
+        L.check(self.lib.lbm_ensemble_step(self.h, int(n), 1 if persistent else 0), "lbm_ensemble_step")
+        return self
+
+    def free(self):
+        if self.h:
+            L.check(self.lib.lbm_ensemble_free(self.h), "lbm_ensemble_free")
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self.h and L._lib is not None:
+                L._lib.lbm_ensemble_free(self.h)
+        except Exception:
+            pass
+
+
+def make_members(specs, form: str = "f32", collision: str = "kbc", variant: str = "B", k0: float = 8,
+                 u_rms: float = 0.05, device="cuda:0") -> list[Sim]:
+    """Sims for (n, nu, seed) specs (see inputs.ensemble_members), each
+    initialised with Grad's approximation of its seeded spectral field."""
+    out = []
+    for n, nu, seed in specs:
+        ux, uy = inputs.spectral(n, k0, u_rms, seed=seed, device=device)
+        s = Sim(n, n, beta_from_nu(nu), collision=collision, variant=variant, form=form, device=device)
+        s.init(ux, uy)
+        out.append(s)
+    torch.cuda.synchronize(device)
+    return out
