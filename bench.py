@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f16": 36, "f32": 72, "f64": 144}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 STEP_SOURCES = [os.path.join(ROOT, "paper_1507_02509_amd", "csrc", f)
-                for f in ("kbc_step.hip", "kbc_device.hpp")]
+                for f in ("kbc_step.hip", "kbc_tile.hpp", "kbc_device.hpp")]
 
 
 def kernel_digest() -> str:
@@ -58,6 +58,10 @@ def measured_traffic(key: str):
         return None
     entry = rec.get("workloads", {}).get(key)
     return None if entry is None else entry.get("bytes_per_launch")
+
+
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def time_steps(sim, steps: int, warmup: int):
@@ -84,6 +88,107 @@ def make_sim(n, form, collision, variant, nu, seed, k0, device):
     sim.init(ux, uy)
     del ux, uy
     return sim
+
+
+def time_adjoint(n, nu, seed, k0, dev, steps=20):
+    """The adjoint step kernel on the same lattice (state f^n fixed, random
+    adjoint field): 9 state loads + 9 adjoint loads + 9 adjoint stores."""
+    import torch
+    sim = make_sim(n, "f32", "kbc", "B", nu, seed, k0, dev)
+    la, lb = sim.new_adjoint(), sim.new_adjoint()
+    la.normal_()
+    acc = torch.zeros(1, dtype=torch.float64, device=dev)
+    state = sim.state_buffer()
+    for _ in range(2):
+        sim.adjoint_step(state, la, lb, acc)
+        la, lb = lb, la
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sim.adjoint_step(state, la, lb, acc)
+        la, lb = lb, la
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del sim, la, lb
+    torch.cuda.empty_cache()
+    return ms
+
+
+def time_c5(dev):
+    """Forward and backward of the differentiable rollout on the adjoint
+    workload: 512^2, KBC-B FP32, 2000 steps, sqrt(N) checkpoints."""
+    import torch
+    from paper_1507_02509_amd import inputs
+    from paper_1507_02509_amd.autograd import rollout
+    from paper_1507_02509_amd.sim import beta_from_nu
+    n, nsteps = 512, 2000
+    ux0, uy0 = (torch.from_numpy(a).to(dev) for a in inputs.spectral(n, 8, 0.05, seed=5))
+    tx, ty = (torch.from_numpy(a).to(dev) for a in inputs.spectral(n, 8, 0.03, seed=55))
+    out = {}
+    for rep in range(2):
+        u0x = ux0.clone().requires_grad_(True)
+        u0y = uy0.clone().requires_grad_(True)
+        b = torch.tensor(beta_from_nu(1e-3), dtype=torch.float64, device=dev, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ux, uy = rollout(u0x, u0y, b, nsteps, form="f32")
+        loss = 0.5 * (((ux - tx) ** 2).sum() + ((uy - ty) ** 2).sum())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out = {"forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+               "backward_over_forward": round((t2 - t1) / (t1 - t0), 3)}
+    return out
+
+
+def time_ensemble(dev, steps=20):
+    """The uneven ensemble: 256 members, N in {128, 256, 512, 1024}, KBC-B FP32,
+    one batched launch per step over all members' tiles."""
+    import torch
+    from paper_1507_02509_amd import inputs
+    from paper_1507_02509_amd.ensemble import Ensemble, make_members
+    specs = inputs.ensemble_members(256, master_seed=4)
+    sims = make_members(specs, form="f32", device=dev)
+    ens = Ensemble(sims)
+    ens.step(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ens.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nodes = ens.nodes
+    ens.free()
+    del ens, sims
+    torch.cuda.empty_cache()
+    return {"members": 256, "nodes": nodes, "ms_per_step": round(ms, 4),
+            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1),
+            "hbm_frac": round(72 * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "launch": "one batched launch per step"}
+
+
+def form_errors(n, nu, seed, k0, dev, steps=10):
+    """Velocity error of the FP32 and FP16 deviation forms against the FP64
+    form after `steps` steps of the same workload (max |du| / max |u|)."""
+    import torch
+    res = {}
+    ref = make_sim(n, "f64", "kbc", "B", nu, seed, k0, dev).step(steps)
+    _, rx, ry = ref.moments()
+    del ref
+    for form in ("f32", "f16"):
+        s = make_sim(n, form, "kbc", "B", nu, seed, k0, dev).step(steps)
+        _, ux, uy = s.moments()
+        del s
+        e = max(float((ux - rx).abs().max() / rx.abs().max()), float((uy - ry).abs().max() / ry.abs().max()))
+        res[form] = e
+        del ux, uy
+        torch.cuda.empty_cache()
+    return {"steps": steps, "u_rel_err_vs_f64": res}
 
 
 def cpu_baseline(n: int, nu: float, seed: int, k0: float, target_s: float = 12.0):
@@ -128,6 +233,8 @@ def main():
     ap.add_argument("--variant", default="B")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="forms,lbgk,copy,adjoint,rollout,ensemble,accuracy",
+                    help="comma-separated extra measurements")
     ap.add_argument("--extra-steps", type=int, default=50,
                     help="timed steps for the other forms and the LBGK baseline")
     args = ap.parse_args()
@@ -144,8 +251,10 @@ def main():
     n, nu, seed, k0 = args.n, 1e-4, 3, 32
     workload = f"d2q9_kbc{args.variant}_turbulence_{n}x{n}_k0_{k0}_nu_1e-4"
 
+    progress(f"init {n}x{n} {args.form} KBC-{args.variant}")
     sim = make_sim(n, args.form, "kbc", args.variant, nu, seed, k0, dev)
     ms, wall = time_steps(sim, args.steps, args.warmup)
+    progress(f"timed {args.steps} steps: {ms:.4f} ms/step")
     d = sim.diagnostics()
     del sim
     torch.cuda.empty_cache()
@@ -156,24 +265,28 @@ def main():
     traffic = measured_traffic(key)
 
     extras = {}
-    if not args.no_extras:
+    want = set() if args.no_extras else set(args.extras.split(","))
+    if want:
         # the same workload in the other storage forms and with the LBGK baseline
         for form in ("f16", "f64"):
-            if form == args.form:
+            if form == args.form or "forms" not in want:
                 continue
             s = make_sim(n, form, "kbc", args.variant, nu, seed, k0, dev)
             m, _ = time_steps(s, args.extra_steps, 2)
+            progress(f"{form}: {m:.4f} ms/step")
             del s
             torch.cuda.empty_cache()
             extras[f"kbc{args.variant}_{form}"] = {
                 "mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4),
                 "hbm_frac": round(BYTES_PER_NODE[form] * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if "lbgk" in want:
         s = make_sim(n, args.form, "lbgk", "A", nu, seed, k0, dev)
         m, _ = time_steps(s, args.extra_steps, 2)
         del s
         torch.cuda.empty_cache()
         extras[f"lbgk_{args.form}"] = {"mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4)}
         extras["kbc_over_lbgk_time"] = round(ms / m, 3)
+    if "copy" in want:
         # the copy reference: 2 x 1.2 GB read + write
         from paper_1507_02509_amd.sim import copy_probe
         a = torch.empty(300_000_000, dtype=torch.float32, device=dev)
@@ -188,8 +301,30 @@ def main():
         torch.cuda.synchronize()
         cms = e0.elapsed_time(e1) / 10
         extras["copy_probe_GBs"] = round(2 * a.numel() * 4 / (cms * 1e-3) / 1e9, 1)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        extras["torch_copy_GBs"] = round(2 * a.numel() * 4 / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9, 1)
         del a, b
         torch.cuda.empty_cache()
+    if "adjoint" in want:
+        progress("adjoint kernel")
+        ams = time_adjoint(n, nu, seed, k0, dev, steps=args.extra_steps)
+        extras["adjoint_f32"] = {"mlups": round(nodes / (ams * 1e-3) / 1e6, 1), "ms_per_step": round(ams, 4),
+                                 "bytes_per_node": 108,
+                                 "hbm_frac": round(108 * nodes / (ams * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "adjoint_over_forward_kernel": round(ams / ms, 3)}
+    if "rollout" in want:
+        progress("rollout 512^2 x 2000")
+        extras["rollout_512_2000_f32"] = time_c5(dev)
+    if "ensemble" in want:
+        progress("ensemble 256")
+        extras["ensemble_256_f32"] = time_ensemble(dev, steps=args.extra_steps)
+    if "accuracy" in want:
+        progress("form errors")
+        extras["accuracy"] = form_errors(n, nu, seed, k0, dev)
 
     out = {
         "metric": METRIC,
@@ -217,6 +352,7 @@ def main():
         "extras": extras,
     }
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(n, nu, seed, k0)
     print(json.dumps(out), flush=True)
 

@@ -210,6 +210,15 @@ int lbm_adjoint_seed(lbm_ctx* c, const void* state, const double* dL_drho, const
  * lam_out = dL/df^n and adds the step's dL/dbeta to *dbeta. */
 int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta);
 
+/* One checkpoint segment of the backward pass: from state0 = f^s, recompute
+ * f^{s+1} .. f^{s+k-1} into slots[0 .. k-2] (population buffers of this
+ * context's layout), then run k adjoint steps from lam_in = dL/df^{s+k} down
+ * to dL/df^s, adding the steps' dL/dbeta to *dbeta.  The two adjoint buffers
+ * are used in turn; *which receives 0 if dL/df^s ended in lam_in and 1 if in
+ * lam_out. */
+int lbm_adjoint_segment(lbm_ctx* c, const void* state0, void* const* slots, int32_t k, void* lam_in,
+                        void* lam_out, double* dbeta, int32_t* which);
+
 /* Adjoint of lbm_init for modes LBM_INIT_EQ and LBM_INIT_GRAD_CD: from
  * lam0 = dL/df^0 and the initial fields (rho nullable = rho0), writes
  * dL/du_x, dL/du_y (dense FP64 [ny][nx]) and adds dL/dbeta of the initial
@@ -247,8 +256,9 @@ int lbm_ensemble_blocks(const lbm_ens* e);
 /* Release the ensemble (never the members).  Synchronises the stream. */
 int lbm_ensemble_free(lbm_ens* e);
 
-/* Streaming copy dst[i] = src[i] of n 4-byte words on `stream`: the bandwidth
- * reference measured beside the step. */
+/* Streaming copy dst[i] = src[i] of n 4-byte words on `stream`, one word per
+ * lane: the bandwidth and profiler-counter reference measured beside the step
+ * (the same access granularity as the step kernel). */
 int lbm_copy_probe(void* dst, const void* src, size_t n_words, void* stream);
 
 #ifdef __cplusplus

@@ -69,13 +69,8 @@ class _Rollout(torch.autograd.Function):
         sim.adjoint_seed(ctx.final, lam_a, grho, gux, guy)
         slots = [sim.new_state() for _ in range(max(0, min(K, N) - 1))]
         for s in sorted(ctx.ckpts.keys(), reverse=True):
-            e = min(s + K, N)
-            states = [ctx.ckpts[s]]
-            for k in range(1, e - s):
-                sim.step_buffers(states[k - 1], slots[k - 1])
-                states.append(slots[k - 1])
-            for n in range(e - 1, s - 1, -1):
-                sim.adjoint_step(states[n - s], lam_a, lam_b, acc)
+            k = min(s + K, N) - s
+            if sim.adjoint_segment(ctx.ckpts[s], slots, k, lam_a, lam_b, acc):
                 lam_a, lam_b = lam_b, lam_a
         gx = torch.empty_like(ux0)
         gy = torch.empty_like(uy0)

@@ -14,6 +14,7 @@
 
 #include "kbc_adjoint.hpp"
 #include "kbc_launch.hpp"
+#include "kbc_tile.hpp"
 
 namespace kbc {
 
@@ -71,60 +72,116 @@ __global__ __launch_bounds__(256) void k_adj_seed(const typename Form<FORM>::S* 
 }
 
 // ----------------------------------------------------------------- adjoint step
+// Grid: one workgroup per tile of 128 x 2 nodes, 8 * rpx * ntx workgroups
+// (workgroup b runs on XCD b % 8).  XCD x owns the rpx tile rows from x * rpx
+// on; its workgroups, which the hardware dispatches in order, take that band's
+// tiles strip by strip (vertical strips of at most kAdjStrip tiles) and
+// row-major within a strip.  The resident workgroups then form a compact front
+// a few strip rows deep, and a cache line that two vertically adjacent tiles
+// share is used again one strip row (under 1 MB of traffic) after its first
+// use, while it is still in the XCD's 4 MB L2; with whole-width rows on a
+// large lattice that distance is about the L2 size and a fifth of the reads
+// miss.  Workgroups left over in a short last band do nothing but write a zero
+// partial.  Each workgroup sums its nodes' dL/dbeta terms in a fixed order
+// into partials[b]; k_fold and k_sum_partials then add them up in a fixed
+// order (no device-scope fence per workgroup: on this GPU such a fence writes
+// back the whole L2 of the XCD).
+constexpr int kAdjStrip = 32;
+constexpr int kFold = 2048;   // partials per k_fold workgroup
+
 template <int FORM, int COLL, int VAR, int GM, bool FROZEN>
 __global__ __launch_bounds__(256) void k_adj_step(const typename Form<FORM>::S* __restrict__ state,
                                                   const typename Form<FORM>::R* __restrict__ lin,
                                                   typename Form<FORM>::R* __restrict__ lout, int nx,
-                                                  int ny, int64_t pitch, int ntx, int ntiles, int per_xcd,
+                                                  int ny, int64_t pitch, int ntx, int nty,
                                                   Coef<typename Form<FORM>::R> K,
                                                   double* __restrict__ partials) {
     using F = Form<FORM>;
     using R = typename F::R;
-    constexpr int TW = 128, WR = 2;   // tile: 128 x 2 nodes, XCD-banded like the forward step
-    const int b = blockIdx.x;
-    const int t = (b & 7) * per_xcd + (b >> 3);
+    using S = typename F::S;
+    constexpr int TW = 128, WR = 2;
+    const int xcd = static_cast<int>(blockIdx.x & 7u), u = static_cast<int>(blockIdx.x >> 3);
+    const int rpx = (nty + 7) >> 3;                            // tile rows per XCD
+    const int row0 = xcd * rpx;
+    const int rows = (nty - row0 < rpx) ? (nty - row0 > 0 ? nty - row0 : 0) : rpx;
+    const int sw = (ntx < kAdjStrip) ? ntx : kAdjStrip;        // strip width in tiles
+    const int full = (ntx / sw) * sw * rows;                   // tiles in full-width strips
+    const int rw = ntx % sw;                                   // width of the last, narrow strip
+    int col = 0, row = 0;
+    if (u < full) {
+        const int s0 = u / (sw * rows), v = u - s0 * (sw * rows);
+        row = v / sw;
+        col = s0 * sw + (v - row * sw);
+    } else if (u < ntx * rows) {
+        const int v = u - full;
+        row = v / rw;
+        col = full / rows + (v - row * rw);
+    }
+    row += row0;
+    const int x = col * TW + static_cast<int>(threadIdx.x % TW);
+    const int y = row * WR + static_cast<int>(threadIdx.x / TW);
     double db = 0.0;
-    if (t < ntiles) {
-        const int tx = t % ntx, ty = t / ntx;
-        const int x = tx * TW + static_cast<int>(threadIdx.x % TW);
-        const int y = ty * WR + static_cast<int>(threadIdx.x / TW);
-        if (x < nx && y < ny) {
-            const int64_t plane = static_cast<int64_t>(ny) * pitch;
-            const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
-            const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
-            const int64_t r0 = static_cast<int64_t>(y) * pitch, rm = static_cast<int64_t>(ym) * pitch,
-                          rp = static_cast<int64_t>(yp) * pitch;
-            R g[9], mu[9], lam[9];
-            // f^n_i(x) sits at x - v_i
-            g[0] = F::dec(state[r0 + x], 0);
-            g[1] = F::dec(state[plane + r0 + xm], 1);
-            g[2] = F::dec(state[2 * plane + rm + x], 2);
-            g[3] = F::dec(state[3 * plane + r0 + xp], 3);
-            g[4] = F::dec(state[4 * plane + rp + x], 4);
-            g[5] = F::dec(state[5 * plane + rm + xm], 5);
-            g[6] = F::dec(state[6 * plane + rm + xp], 6);
-            g[7] = F::dec(state[7 * plane + rp + xp], 7);
-            g[8] = F::dec(state[8 * plane + rp + xm], 8);
-            // mu_i(x) = lam^{n+1}_i(x + v_i)
-            mu[0] = lin[r0 + x];
-            mu[1] = lin[plane + r0 + xp];
-            mu[2] = lin[2 * plane + rp + x];
-            mu[3] = lin[3 * plane + r0 + xm];
-            mu[4] = lin[4 * plane + rm + x];
-            mu[5] = lin[5 * plane + rp + xp];
-            mu[6] = lin[6 * plane + rp + xm];
-            mu[7] = lin[7 * plane + rm + xm];
-            mu[8] = lin[8 * plane + rm + xp];
-            R dbn;
-            collide_vjp<R, COLL, VAR, GM, FROZEN>(g, mu, K, lam, dbn);
-            R* o = lout + r0 + x;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) o[i * plane] = lam[i];
-            db = static_cast<double>(dbn);
-        }
+    if (u < ntx * rows && x < nx && y < ny) {
+        const int64_t plane = static_cast<int64_t>(ny) * pitch;
+        const uint32_t rowS = static_cast<uint32_t>(pitch * static_cast<int64_t>(sizeof(S)));
+        const uint32_t rowR = static_cast<uint32_t>(pitch * static_cast<int64_t>(sizeof(R)));
+        const uint32_t xm = static_cast<uint32_t>((x == 0) ? nx - 1 : x - 1);
+        const uint32_t xp = static_cast<uint32_t>((x == nx - 1) ? 0 : x + 1);
+        const uint32_t ym = static_cast<uint32_t>((y == 0) ? ny - 1 : y - 1);
+        const uint32_t yp = static_cast<uint32_t>((y == ny - 1) ? 0 : y + 1);
+        const uint32_t ux0 = static_cast<uint32_t>(x);
+        const uint32_t uy0 = static_cast<uint32_t>(y);
+        // byte offsets within a plane (planes below 4 GiB)
+        auto os = [&](uint32_t yy, uint32_t xx) { return yy * rowS + xx * static_cast<uint32_t>(sizeof(S)); };
+        auto orr = [&](uint32_t yy, uint32_t xx) { return yy * rowR + xx * static_cast<uint32_t>(sizeof(R)); };
+        R g[9], mu[9], lam[9];
+        // f^n_i(x) sits at x - v_i
+        g[0] = F::dec(ld_at(state, os(uy0, ux0)), 0);
+        g[1] = F::dec(ld_at(state + plane, os(uy0, xm)), 1);
+        g[2] = F::dec(ld_at(state + 2 * plane, os(ym, ux0)), 2);
+        g[3] = F::dec(ld_at(state + 3 * plane, os(uy0, xp)), 3);
+        g[4] = F::dec(ld_at(state + 4 * plane, os(yp, ux0)), 4);
+        g[5] = F::dec(ld_at(state + 5 * plane, os(ym, xm)), 5);
+        g[6] = F::dec(ld_at(state + 6 * plane, os(ym, xp)), 6);
+        g[7] = F::dec(ld_at(state + 7 * plane, os(yp, xp)), 7);
+        g[8] = F::dec(ld_at(state + 8 * plane, os(yp, xm)), 8);
+        // mu_i(x) = lam^{n+1}_i(x + v_i)
+        mu[0] = ld_at(lin, orr(uy0, ux0));
+        mu[1] = ld_at(lin + plane, orr(uy0, xp));
+        mu[2] = ld_at(lin + 2 * plane, orr(yp, ux0));
+        mu[3] = ld_at(lin + 3 * plane, orr(uy0, xm));
+        mu[4] = ld_at(lin + 4 * plane, orr(ym, ux0));
+        mu[5] = ld_at(lin + 5 * plane, orr(yp, xp));
+        mu[6] = ld_at(lin + 6 * plane, orr(yp, xm));
+        mu[7] = ld_at(lin + 7 * plane, orr(ym, xm));
+        mu[8] = ld_at(lin + 8 * plane, orr(ym, xp));
+        R dbn;
+        collide_vjp<R, COLL, VAR, GM, FROZEN>(g, mu, K, lam, dbn);
+        const uint32_t o = orr(uy0, ux0);
+        st_at<false>(uniform_ptr(lout), o, lam[0]);
+        st_at<false>(uniform_ptr(lout + plane), o, lam[1]);
+        st_at<false>(uniform_ptr(lout + 2 * plane), o, lam[2]);
+        st_at<false>(uniform_ptr(lout + 3 * plane), o, lam[3]);
+        st_at<false>(uniform_ptr(lout + 4 * plane), o, lam[4]);
+        st_at<false>(uniform_ptr(lout + 5 * plane), o, lam[5]);
+        st_at<false>(uniform_ptr(lout + 6 * plane), o, lam[6]);
+        st_at<false>(uniform_ptr(lout + 7 * plane), o, lam[7]);
+        st_at<false>(uniform_ptr(lout + 8 * plane), o, lam[8]);
+        db = static_cast<double>(dbn);
     }
     const double s = block_sum(db);
-    if (threadIdx.x == 0) partials[b] = s;
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// out[g] = sum of partials[g * kFold .. (g + 1) * kFold), in a fixed order
+__global__ __launch_bounds__(256) void k_fold(const double* __restrict__ partials, int64_t n,
+                                              double* __restrict__ out) {
+    const int64_t lo = static_cast<int64_t>(blockIdx.x) * kFold;
+    const int64_t hi = (lo + kFold < n) ? lo + kFold : n;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += partials[i];
+    const double t = block_sum(s);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 // acc[0] += sum of n partials, in a fixed order
@@ -214,41 +271,68 @@ __global__ __launch_bounds__(256) void k_adj_init_b(int nx, int ny, const double
 
 int ok() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
+int64_t adj_partials(const Lattice& L) {
+    const int64_t ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;
+    return 8 * ((nty + 7) / 8) * ntx;
+}
+
 template <int FORM, int COLL, int VAR, int GM>
 struct AdjStepOp {
     static int run(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                   int64_t nblocks_cap, double* acc) {
+                   double* folds, double* acc) {
         using F = Form<FORM>;
         using R = typename F::R;
         const int ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;
-        const int64_t nt64 = static_cast<int64_t>(ntx) * nty;
-        if (nt64 > (int64_t{1} << 30)) return -1;
-        const int ntiles = static_cast<int>(nt64);
-        const int per_xcd = (ntiles + 7) / 8;
-        const int64_t nblocks = 8 * static_cast<int64_t>(per_xcd);
-        if (nblocks > nblocks_cap) return -1;
+        const int64_t nb = adj_partials(L);
+        if (static_cast<int64_t>(ntx) * nty > (int64_t{1} << 30) || nb > (int64_t{1} << 31) - 1) return -1;
+        const dim3 grid(static_cast<unsigned>(nb)), block(256);
         if (L.adj_frozen)
-            k_adj_step<FORM, COLL, VAR, GM, true><<<dim3(static_cast<unsigned>(nblocks)), dim3(256), 0, L.stream>>>(
+            k_adj_step<FORM, COLL, VAR, GM, true><<<grid, block, 0, L.stream>>>(
                 static_cast<const typename F::S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx,
-                L.ny, L.pitch, ntx, ntiles, per_xcd, make_coef<R>(L), partials);
+                L.ny, L.pitch, ntx, nty, make_coef<R>(L), partials);
         else
-            k_adj_step<FORM, COLL, VAR, GM, false><<<dim3(static_cast<unsigned>(nblocks)), dim3(256), 0, L.stream>>>(
+            k_adj_step<FORM, COLL, VAR, GM, false><<<grid, block, 0, L.stream>>>(
                 static_cast<const typename F::S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx,
-                L.ny, L.pitch, ntx, ntiles, per_xcd, make_coef<R>(L), partials);
+                L.ny, L.pitch, ntx, nty, make_coef<R>(L), partials);
         if (ok()) return -2;
-        if (acc) {
-            k_sum_partials<<<1, 256, 0, L.stream>>>(partials, nblocks, acc);
+        if (folds) {
+            const int64_t ng = (nb + kFold - 1) / kFold;
+            k_fold<<<dim3(static_cast<unsigned>(ng)), dim3(256), 0, L.stream>>>(partials, nb, folds);
             if (ok()) return -2;
+            if (acc) {
+                k_sum_partials<<<1, 256, 0, L.stream>>>(folds, ng, acc);
+                if (ok()) return -2;
+            }
         }
         return 0;
     }
 };
 
+// acc[0] += sum of slice n, for n = k-1 down to 0 (the order in which the
+// segment's adjoint steps ran), each slice reduced exactly as k_sum_partials
+// does: the result is bitwise the same as summing after every step.
+__global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ slices, int64_t ng, int k,
+                                                    double* __restrict__ acc) {
+    for (int n = k - 1; n >= 0; --n) {
+        const double* p = slices + static_cast<int64_t>(n) * ng;
+        double s = 0.0;
+        for (int64_t i = threadIdx.x; i < ng; i += 256) s += p[i];
+        const double t = block_sum(s);
+        if (threadIdx.x == 0) acc[0] += t;
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
-int64_t adjoint_step_blocks(const Lattice& L) {
-    const int64_t ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;
-    return 8 * ((ntx * nty + 7) / 8);
+// per-workgroup partials of one adjoint step, and the folded sums of those
+int64_t adjoint_partials(const Lattice& L) { return adj_partials(L); }
+int64_t adjoint_folds(const Lattice& L) { return (adj_partials(L) + kFold - 1) / kFold; }
+
+int launch_sum_slices(const double* slices, int64_t ng, int k, double* acc, hipStream_t stream) {
+    if (!acc || ng <= 0 || k <= 0) return 0;
+    k_sum_slices<<<1, 256, 0, stream>>>(slices, ng, k, acc);
+    return ok();
 }
 
 int launch_adjoint_seed(const Lattice& L, const void* state, const double* drho, const double* dux,
@@ -264,8 +348,8 @@ int launch_adjoint_seed(const Lattice& L, const void* state, const double* drho,
 }
 
 int launch_adjoint_step(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                        int64_t nblocks_cap, double* acc) {
-    return dispatch<AdjStepOp>(L, state, lin, lout, partials, nblocks_cap, acc);
+                        double* folds, double* acc) {
+    return dispatch<AdjStepOp>(L, state, lin, lout, partials, folds, acc);
 }
 
 int launch_adjoint_init(const Lattice& L, const double* rho, const double* ux, const double* uy, int mode,

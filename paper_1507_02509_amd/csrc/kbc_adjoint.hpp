@@ -227,17 +227,22 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
     jxb = fmaR(uxb, ir, jxb);
     jyb = fmaR(uyb, ir, jyb);
     drb -= (uxb * ux + uyb * uy) * ir;
-    // dr = sum g, j = sum c g, and the raw sums of g
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const R cx = R(kCx[i]), cy = R(kCy[i]);
-        R s = drb + cx * jxb + cy * jyb;
-        if constexpr (COLL != LBGK) {
-            s += cx * cx * Sxxb + cy * cy * Syyb + cx * cy * Sxyb + cx * cy * cy * Qxrb +
-                 cx * cx * cy * Qyrb + cx * cx * cy * cy * Arb;
-        }
-        lam[i] += s;
-    }
+    // dr = sum g, j = sum c g, and the raw sums of g:
+    // lam_i += drb + c_x jxb + c_y jyb + c_x^2 Sxxb + c_y^2 Syyb + c_x c_y Sxyb
+    //          + c_x c_y^2 Qxrb + c_x^2 c_y Qyrb + c_x^2 c_y^2 Arb
+    const R ax = drb + Sxxb, ay = drb + Syyb;
+    const R dd = (ax + Syyb) + Arb;               // common to the diagonals
+    const R px = jxb + Qxrb, py = jyb + Qyrb;
+    lam[0] += drb;
+    lam[1] += ax + jxb;
+    lam[3] += ax - jxb;
+    lam[2] += ay + jyb;
+    lam[4] += ay - jyb;
+    const R dp = dd + Sxyb, dm = dd - Sxyb;
+    lam[5] += dp + (px + py);
+    lam[7] += dp - (px + py);
+    lam[6] += dm - (px - py);
+    lam[8] += dm + (px - py);
 }
 
 }  // namespace kbc

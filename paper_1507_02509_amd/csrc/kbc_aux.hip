@@ -276,29 +276,12 @@ __global__ __launch_bounds__(256) void k_diag_c(int nx, int ny, const double* __
 }
 
 // ------------------------------------------------------------ copy reference
-// Each workgroup copies one contiguous chunk of 256 * kCopyUnroll float4; a
-// thread keeps kCopyUnroll independent 16-byte loads in flight before storing.
-constexpr int kCopyUnroll = 8;
-
-__global__ __launch_bounds__(256) void k_copy(float4* __restrict__ dst, const float4* __restrict__ src,
-                                              int64_t n4) {
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * (256 * kCopyUnroll) + threadIdx.x;
-    float4 v[kCopyUnroll];
-#pragma unroll
-    for (int u = 0; u < kCopyUnroll; ++u) {
-        const int64_t i = base + u * 256;
-        if (i < n4) v[u] = src[i];
-    }
-#pragma unroll
-    for (int u = 0; u < kCopyUnroll; ++u) {
-        const int64_t i = base + u * 256;
-        if (i < n4) dst[i] = v[u];
-    }
-}
-
-__global__ void k_copy_tail(float* __restrict__ dst, const float* __restrict__ src, int64_t start,
-                            int64_t n) {
-    const int64_t i = start + threadIdx.x;
+// The plainest streaming copy: one 4-byte word per lane, one pass, the same
+// access granularity as the step kernel's loads and stores.  It is the
+// reference both for achievable bandwidth and for scaling the HBM byte
+// counters of the profiler.
+__global__ __launch_bounds__(256) void k_copy(float* __restrict__ dst, const float* __restrict__ src, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (i < n) dst[i] = src[i];
 }
 
@@ -381,21 +364,12 @@ int launch_diag(const Lattice& L, const void* src, double* ux_s, double* uy_s, d
 }
 
 int launch_copy(void* dst, const void* src, size_t n_words, hipStream_t stream) {
-    const int64_t n4 = static_cast<int64_t>(n_words / 4);
-    if (n4 > 0) {
-        const int64_t blocks = (n4 + 256 * kCopyUnroll - 1) / (256 * kCopyUnroll);
-        if (blocks > (int64_t{1} << 31) - 1) return -1;
-        k_copy<<<static_cast<unsigned>(blocks), 256, 0, stream>>>(static_cast<float4*>(dst),
-                                                                  static_cast<const float4*>(src), n4);
-        if (ok_launch()) return -2;
-    }
-    const int64_t done = n4 * 4;
-    if (static_cast<int64_t>(n_words) > done) {
-        k_copy_tail<<<1, 64, 0, stream>>>(static_cast<float*>(dst), static_cast<const float*>(src), done,
-                                         static_cast<int64_t>(n_words));
-        if (ok_launch()) return -2;
-    }
-    return 0;
+    const int64_t n = static_cast<int64_t>(n_words);
+    if (n == 0) return 0;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > (int64_t{1} << 31) - 1) return -1;
+    k_copy<<<static_cast<unsigned>(blocks), 256, 0, stream>>>(static_cast<float*>(dst), static_cast<const float*>(src), n);
+    return ok_launch();
 }
 
 }  // namespace kbc

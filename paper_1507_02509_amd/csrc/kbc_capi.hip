@@ -341,11 +341,47 @@ int lbm_adjoint_seed(lbm_ctx* c, const void* state, const double* dL_drho, const
 int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta) {
     if (!c || !state || !lam_in || !lam_out || lam_in == lam_out)
         return fail(LBM_EINVAL, "ctx, state and two distinct adjoint buffers are required");
-    const int64_t nb = kbc::adjoint_step_blocks(c->L);
-    int rc = ensure_ascratch(c, static_cast<size_t>(nb));
+    const int64_t nb = kbc::adjoint_partials(c->L), ng = kbc::adjoint_folds(c->L);
+    int rc = ensure_ascratch(c, static_cast<size_t>(nb + ng));
     if (rc) return rc;
-    return launch_result(kbc::launch_adjoint_step(c->L, state, lam_in, lam_out, c->ascratch, nb, dbeta),
+    return launch_result(kbc::launch_adjoint_step(c->L, state, lam_in, lam_out, c->ascratch,
+                                                  dbeta ? c->ascratch + nb : nullptr, dbeta),
                          "lbm_adjoint_step");
+}
+
+int lbm_adjoint_segment(lbm_ctx* c, const void* state0, void* const* slots, int32_t k, void* lam_in,
+                        void* lam_out, double* dbeta, int32_t* which) {
+    if (!c || !state0 || k < 1 || (k > 1 && !slots) || !lam_in || !lam_out || lam_in == lam_out || !which)
+        return fail(LBM_EINVAL, "invalid adjoint segment arguments");
+    for (int32_t i = 0; i + 1 < k; ++i)
+        if (!slots[i]) return fail(LBM_EINVAL, "slot %d is NULL", i);
+    // every adjoint step of the segment folds its partials into a slice of
+    // its own; one reduction at the end adds the slices, in step order, to
+    // *dbeta
+    const int64_t nb = kbc::adjoint_partials(c->L), ng = kbc::adjoint_folds(c->L);
+    int rc = ensure_ascratch(c, static_cast<size_t>(nb + ng * k));
+    if (rc) return rc;
+    // recompute f^{s+1} .. f^{s+k-1}
+    for (int32_t i = 1; i < k; ++i) {
+        const void* src = (i == 1) ? state0 : slots[i - 2];
+        rc = kbc::launch_step(c->L, src, slots[i - 1], c->shape);
+        if (rc) return launch_result(rc, "lbm_adjoint_segment recompute");
+    }
+    void* a = lam_in;
+    void* b = lam_out;
+    for (int32_t n = k - 1; n >= 0; --n) {
+        const void* st = (n == 0) ? state0 : slots[n - 1];
+        rc = kbc::launch_adjoint_step(c->L, st, a, b, c->ascratch,
+                                      dbeta ? c->ascratch + nb + static_cast<int64_t>(n) * ng : nullptr, nullptr);
+        if (rc) return launch_result(rc, "lbm_adjoint_segment");
+        void* t = a;
+        a = b;
+        b = t;
+    }
+    rc = kbc::launch_sum_slices(c->ascratch + nb, ng, k, dbeta, c->L.stream);
+    if (rc) return launch_result(rc, "lbm_adjoint_segment sum");
+    *which = (a == lam_in) ? 0 : 1;
+    return LBM_OK;
 }
 
 int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const double* uy, int32_t mode,
@@ -356,10 +392,12 @@ int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const doub
         return fail(LBM_EUNSUPPORTED, "adjoint of init mode %d is not built", mode);
     const size_t N = static_cast<size_t>(c->p.nx) * c->p.ny;
     const size_t nb = (N + 255) / 256;
-    int rc = ensure_ascratch(c, nb + 4 * N);
+    // the adjoint step's partials and folds come first
+    const size_t off = static_cast<size_t>(kbc::adjoint_partials(c->L) + kbc::adjoint_folds(c->L));
+    int rc = ensure_ascratch(c, off + nb + 4 * N);
     if (rc) return rc;
     return launch_result(kbc::launch_adjoint_init(c->L, rho, ux, uy, mode == LBM_INIT_GRAD_CD ? 1 : 0, lam0,
-                                                  grad_ux, grad_uy, c->ascratch + nb, c->ascratch,
+                                                  grad_ux, grad_uy, c->ascratch + off + nb, c->ascratch + off,
                                                   static_cast<int64_t>(nb), dbeta),
                          "lbm_adjoint_init");
 }

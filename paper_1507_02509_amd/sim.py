@@ -153,6 +153,15 @@ class Sim:
         L.check(self.lib.lbm_adjoint_step(self.ctx, L.ptr(state), L.ptr(lam_in), L.ptr(lam_out), L.ptr(dbeta)),
                 "lbm_adjoint_step")
 
+    def adjoint_segment(self, state0, slots, k: int, lam_in, lam_out, dbeta=None) -> int:
+        """Recompute and back-propagate one checkpoint segment (see
+        lbm_adjoint_segment); returns 0 if the result is in lam_in, 1 if in lam_out."""
+        arr = (ctypes.c_void_p * max(1, k - 1))(*[L.ptr(t) for t in slots[:k - 1]]) if k > 1 else None
+        which = ctypes.c_int32(-1)
+        L.check(self.lib.lbm_adjoint_segment(self.ctx, L.ptr(state0), arr, int(k), L.ptr(lam_in), L.ptr(lam_out),
+                                             L.ptr(dbeta), ctypes.byref(which)), "lbm_adjoint_segment")
+        return int(which.value)
+
     def adjoint_init(self, ux0, uy0, lam0, grad_ux, grad_uy, dbeta=None, rho=None, mode: str = "grad_cd"):
         L.check(self.lib.lbm_adjoint_init(self.ctx, L.ptr(rho), L.ptr(ux0), L.ptr(uy0), _INIT[mode], L.ptr(lam0),
                                           L.ptr(grad_ux), L.ptr(grad_uy), L.ptr(dbeta)), "lbm_adjoint_init")
