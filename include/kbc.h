@@ -21,8 +21,9 @@
  *   (-1,-1) (1,-1); weights W = 4/9, 1/9 (x4), 1/36 (x4); periodic in x and y.
  *
  * Storage (device memory owned by the caller, e.g. torch tensors):
- *   a population buffer is 9 planes of ny rows of `pitch` elements, element
- *   (i, y, x) at offset (i * ny + y) * pitch + x, x fastest.  The stored value
+ *   a population buffer holds, for every lattice row y, the nine population
+ *   rows of `pitch` elements one after another ([ny][9][pitch], x fastest):
+ *   element (i, y, x) at offset (9 * y + i) * pitch + x.  The stored value
  *   is the deviation g_i = f_i - W_i rho0 in the form's storage type:
  *     LBM_F16DEV_F32: binary16 holding g_i * 2^s_i (s = 1 for i = 0, 3 for the
  *                     axis velocities, 5 for the diagonals), FP32 arithmetic;
@@ -153,8 +154,8 @@ void* lbm_work_buffer(const lbm_ctx* c);
 
 /* Workgroup tile of the step kernel: `width` in {64, 128, 256} nodes by
  * (256 / width) * rows_per_thread rows, rows_per_thread in {1, 2, 4}
- * (default per form: 64 x 16 non-temporal for FP16, 256 x 2 for FP32,
- * 256 x 2 non-temporal for FP64); flags: LBM_TILE_NONTEMPORAL writes the new state with
+ * (default per form, all non-temporal: 256 x 4 for FP16, 256 x 1 for FP32,
+ * 128 x 2 for FP64); flags: LBM_TILE_NONTEMPORAL writes the new state with
  * non-temporal stores.  A tuning knob only: results are bitwise identical for
  * every setting. */
 #define LBM_TILE_NONTEMPORAL 1
@@ -175,7 +176,7 @@ const char* lbm_last_error(void);
  * velocity and beta (discrete adjoint of eq. (Egeneral) with the collision of
  * this context, gamma(f) of eq. (result21) differentiated; constant where the
  * guard selects gamma = 2).  An adjoint buffer holds dL/df for every node and
- * velocity, [9][ny][pitch] in the form's arithmetic type (float for the two
+ * velocity, [ny][9][pitch] in the form's arithmetic type (float for the two
  * deviation forms, double for LBM_F64), NOT shifted: element (i, y, x) is
  * dL/df_i(x, y).  `state` arguments are population buffers in this context's
  * layout holding f(x, t = n) (e.g. checkpoints copied from lbm_state_buffer).
@@ -229,7 +230,7 @@ int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const doub
 /* ----------------------------------------------------------------- ensemble
  * Many independent lattices (e.g. of different sizes and beta) advanced
  * together.  An ensemble borrows member contexts created with lbm_init (same
- * form, collision, variant, stabiliser mode and stream; planes below 4 GiB)
+ * form, collision, variant, stabiliser mode and stream)
  * and steps all of them; each member keeps its own buffers, parameters and
  * entry points (moments, populations, diagnostics).  Stepping is bitwise
  * identical to calling lbm_step on every member. */

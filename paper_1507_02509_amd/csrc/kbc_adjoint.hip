@@ -9,7 +9,8 @@
 // An adjoint step reads f^n (nine shifted loads from the state buffer, as the
 // forward step does), mu_i(x) = lam^{n+1}_i(x + v_i) (nine loads shifted the
 // other way) and writes lam^n at x: 27 accesses per node.  Adjoint fields are
-// stored [9][ny][pitch] in the form's arithmetic type, unshifted.
+// stored like the state, [ny][9][pitch], in the form's arithmetic type,
+// unshifted.
 #include <type_traits>
 
 #include "kbc_adjoint.hpp"
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(256) void k_adj_seed(const typename Form<FORM>::S* 
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const int xs = wrapi(x - kCx[i], nx), ys = wrapi(y - kCy[i], ny);
-        const double g = F::dec64(state[(static_cast<int64_t>(i) * ny + ys) * pitch + xs], i);
+        const double g = F::dec64(state[(static_cast<int64_t>(ys) * 9 + i) * pitch + xs], i);
         dr += g;
         jx += kCx[i] * g;
         jy += kCy[i] * g;
@@ -64,11 +65,10 @@ __global__ __launch_bounds__(256) void k_adj_seed(const typename Form<FORM>::S* 
     const int64_t n = static_cast<int64_t>(y) * nx + x;
     const double a = drho ? drho[n] : 0.0;
     const double bx = dux ? dux[n] : 0.0, by = duy ? duy[n] : 0.0;
-    const int64_t plane = static_cast<int64_t>(ny) * pitch;
-    R* o = lam + static_cast<int64_t>(y) * pitch + x;
+    R* o = lam + static_cast<int64_t>(y) * 9 * pitch + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        o[i * plane] = static_cast<R>(a + (bx * (kCx[i] - u) + by * (kCy[i] - v)) / r);
+        o[i * pitch] = static_cast<R>(a + (bx * (kCx[i] - u) + by * (kCy[i] - v)) / r);
 }
 
 // ----------------------------------------------------------------- adjoint step
@@ -83,8 +83,8 @@ __global__ __launch_bounds__(256) void k_adj_seed(const typename Form<FORM>::S* 
 // large lattice that distance is about the L2 size and a fifth of the reads
 // miss.  Workgroups left over in a short last band do nothing but write a zero
 // partial.  Each workgroup sums its nodes' dL/dbeta terms in a fixed order
-// into partials[b]; k_fold and k_sum_partials then add them up in a fixed
-// order (no device-scope fence per workgroup: on this GPU such a fence writes
+// into partials[b]; on large lattices k_fold shortens that array first, and
+// k_sum_partials adds it up in a fixed order (no device-scope fence per workgroup: on this GPU such a fence writes
 // back the whole L2 of the XCD).
 constexpr int kAdjStrip = 32;
 constexpr int kFold = 2048;   // partials per k_fold workgroup
@@ -122,51 +122,39 @@ __global__ __launch_bounds__(256) void k_adj_step(const typename Form<FORM>::S* 
     const int y = row * WR + static_cast<int>(threadIdx.x / TW);
     double db = 0.0;
     if (u < ntx * rows && x < nx && y < ny) {
-        const int64_t plane = static_cast<int64_t>(ny) * pitch;
-        const uint32_t rowS = static_cast<uint32_t>(pitch * static_cast<int64_t>(sizeof(S)));
-        const uint32_t rowR = static_cast<uint32_t>(pitch * static_cast<int64_t>(sizeof(R)));
+        // y is uniform across the wave (a wave covers 64 nodes of one row)
+        const int yu = __builtin_amdgcn_readfirstlane(y);
+        const int ym = (yu == 0) ? ny - 1 : yu - 1;
+        const int yp = (yu == ny - 1) ? 0 : yu + 1;
         const uint32_t xm = static_cast<uint32_t>((x == 0) ? nx - 1 : x - 1);
         const uint32_t xp = static_cast<uint32_t>((x == nx - 1) ? 0 : x + 1);
-        const uint32_t ym = static_cast<uint32_t>((y == 0) ? ny - 1 : y - 1);
-        const uint32_t yp = static_cast<uint32_t>((y == ny - 1) ? 0 : y + 1);
-        const uint32_t ux0 = static_cast<uint32_t>(x);
-        const uint32_t uy0 = static_cast<uint32_t>(y);
-        // byte offsets within a plane (planes below 4 GiB)
-        auto os = [&](uint32_t yy, uint32_t xx) { return yy * rowS + xx * static_cast<uint32_t>(sizeof(S)); };
-        auto orr = [&](uint32_t yy, uint32_t xx) { return yy * rowR + xx * static_cast<uint32_t>(sizeof(R)); };
+        const uint32_t sS = sizeof(S), sR = sizeof(R);
+        const uint32_t x0 = static_cast<uint32_t>(x);
         R g[9], mu[9], lam[9];
         // f^n_i(x) sits at x - v_i
-        g[0] = F::dec(ld_at(state, os(uy0, ux0)), 0);
-        g[1] = F::dec(ld_at(state + plane, os(uy0, xm)), 1);
-        g[2] = F::dec(ld_at(state + 2 * plane, os(ym, ux0)), 2);
-        g[3] = F::dec(ld_at(state + 3 * plane, os(uy0, xp)), 3);
-        g[4] = F::dec(ld_at(state + 4 * plane, os(yp, ux0)), 4);
-        g[5] = F::dec(ld_at(state + 5 * plane, os(ym, xm)), 5);
-        g[6] = F::dec(ld_at(state + 6 * plane, os(ym, xp)), 6);
-        g[7] = F::dec(ld_at(state + 7 * plane, os(yp, xp)), 7);
-        g[8] = F::dec(ld_at(state + 8 * plane, os(yp, xm)), 8);
+        g[0] = F::dec(ld_at(row_ptr(state, yu, 0, pitch), x0 * sS), 0);
+        g[1] = F::dec(ld_at(row_ptr(state, yu, 1, pitch), xm * sS), 1);
+        g[2] = F::dec(ld_at(row_ptr(state, ym, 2, pitch), x0 * sS), 2);
+        g[3] = F::dec(ld_at(row_ptr(state, yu, 3, pitch), xp * sS), 3);
+        g[4] = F::dec(ld_at(row_ptr(state, yp, 4, pitch), x0 * sS), 4);
+        g[5] = F::dec(ld_at(row_ptr(state, ym, 5, pitch), xm * sS), 5);
+        g[6] = F::dec(ld_at(row_ptr(state, ym, 6, pitch), xp * sS), 6);
+        g[7] = F::dec(ld_at(row_ptr(state, yp, 7, pitch), xp * sS), 7);
+        g[8] = F::dec(ld_at(row_ptr(state, yp, 8, pitch), xm * sS), 8);
         // mu_i(x) = lam^{n+1}_i(x + v_i)
-        mu[0] = ld_at(lin, orr(uy0, ux0));
-        mu[1] = ld_at(lin + plane, orr(uy0, xp));
-        mu[2] = ld_at(lin + 2 * plane, orr(yp, ux0));
-        mu[3] = ld_at(lin + 3 * plane, orr(uy0, xm));
-        mu[4] = ld_at(lin + 4 * plane, orr(ym, ux0));
-        mu[5] = ld_at(lin + 5 * plane, orr(yp, xp));
-        mu[6] = ld_at(lin + 6 * plane, orr(yp, xm));
-        mu[7] = ld_at(lin + 7 * plane, orr(ym, xm));
-        mu[8] = ld_at(lin + 8 * plane, orr(ym, xp));
+        mu[0] = ld_at(row_ptr(lin, yu, 0, pitch), x0 * sR);
+        mu[1] = ld_at(row_ptr(lin, yu, 1, pitch), xp * sR);
+        mu[2] = ld_at(row_ptr(lin, yp, 2, pitch), x0 * sR);
+        mu[3] = ld_at(row_ptr(lin, yu, 3, pitch), xm * sR);
+        mu[4] = ld_at(row_ptr(lin, ym, 4, pitch), x0 * sR);
+        mu[5] = ld_at(row_ptr(lin, yp, 5, pitch), xp * sR);
+        mu[6] = ld_at(row_ptr(lin, yp, 6, pitch), xm * sR);
+        mu[7] = ld_at(row_ptr(lin, ym, 7, pitch), xm * sR);
+        mu[8] = ld_at(row_ptr(lin, ym, 8, pitch), xp * sR);
         R dbn;
         collide_vjp<R, COLL, VAR, GM, FROZEN>(g, mu, K, lam, dbn);
-        const uint32_t o = orr(uy0, ux0);
-        st_at<false>(uniform_ptr(lout), o, lam[0]);
-        st_at<false>(uniform_ptr(lout + plane), o, lam[1]);
-        st_at<false>(uniform_ptr(lout + 2 * plane), o, lam[2]);
-        st_at<false>(uniform_ptr(lout + 3 * plane), o, lam[3]);
-        st_at<false>(uniform_ptr(lout + 4 * plane), o, lam[4]);
-        st_at<false>(uniform_ptr(lout + 5 * plane), o, lam[5]);
-        st_at<false>(uniform_ptr(lout + 6 * plane), o, lam[6]);
-        st_at<false>(uniform_ptr(lout + 7 * plane), o, lam[7]);
-        st_at<false>(uniform_ptr(lout + 8 * plane), o, lam[8]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st_at<false>(row_ptr(lout, yu, i, pitch), x0 * sR, lam[i]);
         db = static_cast<double>(dbn);
     }
     const double s = block_sum(db);
@@ -214,10 +202,9 @@ __global__ __launch_bounds__(256) void k_adj_init_a(const R* __restrict__ lam, i
         const int y = static_cast<int>(n / nx), x = static_cast<int>(n - static_cast<int64_t>(y) * nx);
         const double r = rho ? rho[n] : rho0;
         const double u = ux[n], v = uy[n];
-        const int64_t plane = static_cast<int64_t>(ny) * pitch;
         double l[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) l[i] = static_cast<double>(lam[i * plane + static_cast<int64_t>(y) * pitch + x]);
+        for (int i = 0; i < 9; ++i) l[i] = static_cast<double>(lam[(static_cast<int64_t>(y) * 9 + i) * pitch + x]);
         double gx = 0.0, gy = 0.0, sxx = 0.0, syy = 0.0, sxy = 0.0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -271,67 +258,88 @@ __global__ __launch_bounds__(256) void k_adj_init_b(int nx, int ny, const double
 
 int ok() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
-int64_t adj_partials(const Lattice& L) {
+// Workgroups of one adjoint step (= per-workgroup partials it writes).
+int64_t adj_blocks(const Lattice& L) {
     const int64_t ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;
     return 8 * ((nty + 7) / 8) * ntx;
+}
+
+// Up to kDirect workgroups the partials are the step's slice; beyond, they
+// are folded by kFold into a shorter slice (one more launch per step, which
+// small lattices, limited by launch rate, should not pay).
+constexpr int64_t kDirect = 16384;
+int64_t adj_slice_len(const Lattice& L) {
+    const int64_t nb = adj_blocks(L);
+    return nb <= kDirect ? nb : (nb + kFold - 1) / kFold;
 }
 
 template <int FORM, int COLL, int VAR, int GM>
 struct AdjStepOp {
     static int run(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                   double* folds, double* acc) {
+                   double* slice, double* acc) {
         using F = Form<FORM>;
         using R = typename F::R;
         const int ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;
-        const int64_t nb = adj_partials(L);
+        const int64_t nb = adj_blocks(L);
         if (static_cast<int64_t>(ntx) * nty > (int64_t{1} << 30) || nb > (int64_t{1} << 31) - 1) return -1;
+        const bool direct = nb <= kDirect;
+        if (!slice || (!direct && !partials)) return -1;
+        double* out = direct ? slice : partials;
         const dim3 grid(static_cast<unsigned>(nb)), block(256);
         if (L.adj_frozen)
             k_adj_step<FORM, COLL, VAR, GM, true><<<grid, block, 0, L.stream>>>(
                 static_cast<const typename F::S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx,
-                L.ny, L.pitch, ntx, nty, make_coef<R>(L), partials);
+                L.ny, L.pitch, ntx, nty, make_coef<R>(L), out);
         else
             k_adj_step<FORM, COLL, VAR, GM, false><<<grid, block, 0, L.stream>>>(
                 static_cast<const typename F::S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx,
-                L.ny, L.pitch, ntx, nty, make_coef<R>(L), partials);
+                L.ny, L.pitch, ntx, nty, make_coef<R>(L), out);
         if (ok()) return -2;
-        if (folds) {
-            const int64_t ng = (nb + kFold - 1) / kFold;
-            k_fold<<<dim3(static_cast<unsigned>(ng)), dim3(256), 0, L.stream>>>(partials, nb, folds);
+        const int64_t len = adj_slice_len(L);
+        if (!direct) {
+            k_fold<<<dim3(static_cast<unsigned>(len)), dim3(256), 0, L.stream>>>(partials, nb, slice);
             if (ok()) return -2;
-            if (acc) {
-                k_sum_partials<<<1, 256, 0, L.stream>>>(folds, ng, acc);
-                if (ok()) return -2;
-            }
+        }
+        if (acc) {
+            k_sum_partials<<<1, 256, 0, L.stream>>>(slice, len, acc);
+            if (ok()) return -2;
         }
         return 0;
     }
 };
 
-// acc[0] += sum of slice n, for n = k-1 down to 0 (the order in which the
-// segment's adjoint steps ran), each slice reduced exactly as k_sum_partials
-// does: the result is bitwise the same as summing after every step.
-__global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ slices, int64_t ng, int k,
-                                                    double* __restrict__ acc) {
-    for (int n = k - 1; n >= 0; --n) {
-        const double* p = slices + static_cast<int64_t>(n) * ng;
-        double s = 0.0;
-        for (int64_t i = threadIdx.x; i < ng; i += 256) s += p[i];
-        const double t = block_sum(s);
-        if (threadIdx.x == 0) acc[0] += t;
-        __syncthreads();
-    }
+// tot[n] = sum of slice n, reduced exactly as k_sum_partials reduces a slice
+// (one workgroup per slice)
+__global__ __launch_bounds__(256) void k_slice_sums(const double* __restrict__ slices, int64_t len,
+                                                    double* __restrict__ tot) {
+    const double* p = slices + static_cast<int64_t>(blockIdx.x) * len;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < len; i += 256) s += p[i];
+    const double t = block_sum(s);
+    if (threadIdx.x == 0) tot[blockIdx.x] = t;
+}
+
+// acc[0] += tot[n] for n = k-1 down to 0, the order in which the segment's
+// adjoint steps ran: bitwise the same as adding each step's sum after it.
+__global__ void k_add_in_order(const double* __restrict__ tot, int k, double* __restrict__ acc) {
+    if (threadIdx.x != 0) return;
+    double a = acc[0];
+    for (int n = k - 1; n >= 0; --n) a += tot[n];
+    acc[0] = a;
 }
 
 }  // namespace
 
-// per-workgroup partials of one adjoint step, and the folded sums of those
-int64_t adjoint_partials(const Lattice& L) { return adj_partials(L); }
-int64_t adjoint_folds(const Lattice& L) { return (adj_partials(L) + kFold - 1) / kFold; }
+// scratch doubles for the unfolded partials of one adjoint step (0 when the
+// partials are the slice itself), and the length of a step's slice
+int64_t adjoint_partials(const Lattice& L) { return adj_blocks(L) <= kDirect ? 0 : adj_blocks(L); }
+int64_t adjoint_slice_len(const Lattice& L) { return adj_slice_len(L); }
 
-int launch_sum_slices(const double* slices, int64_t ng, int k, double* acc, hipStream_t stream) {
-    if (!acc || ng <= 0 || k <= 0) return 0;
-    k_sum_slices<<<1, 256, 0, stream>>>(slices, ng, k, acc);
+int launch_sum_slices(const double* slices, int64_t len, int k, double* tot, double* acc, hipStream_t stream) {
+    if (!acc || len <= 0 || k <= 0) return 0;
+    k_slice_sums<<<dim3(static_cast<unsigned>(k)), dim3(256), 0, stream>>>(slices, len, tot);
+    if (ok()) return -2;
+    k_add_in_order<<<1, 64, 0, stream>>>(tot, k, acc);
     return ok();
 }
 
@@ -348,8 +356,8 @@ int launch_adjoint_seed(const Lattice& L, const void* state, const double* drho,
 }
 
 int launch_adjoint_step(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                        double* folds, double* acc) {
-    return dispatch<AdjStepOp>(L, state, lin, lout, partials, folds, acc);
+                        double* slice, double* acc) {
+    return dispatch<AdjStepOp>(L, state, lin, lout, partials, slice, acc);
 }
 
 int launch_adjoint_init(const Lattice& L, const double* rho, const double* ux, const double* uy, int mode,

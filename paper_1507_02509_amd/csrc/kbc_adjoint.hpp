@@ -153,75 +153,80 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
         }
 
         // --------------------------------------------------------- reverse
-        // g'_i = g_i - 2 beta ds_i - beta gamma dh_i
-        R dsb[9], dhb[9];
-        R gamb = R(0), db = R(0);
-        const R tb = R(2) * K.beta, bg = K.beta * gam;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            lam[i] = mu[i];
-            dsb[i] = -tb * mu[i];
-            dhb[i] = -bg * mu[i];
-            gamb = fmaR(mu[i], dh[i], gamb);
-            db = fmaR(mu[i], fmaR(gam, dh[i], R(2) * ds[i]), db);
-        }
-        gamb = -K.beta * gamb;
-        dbeta = -db;
-        if constexpr (GM != GFIX && !FROZEN) {
-            if (active) {
-                // gamma = 1/beta - (2 - 1/beta) a / b
-                const R ib2 = K.inv_beta * K.inv_beta;
-                dbeta = fmaR(gamb, -(R(1) + ratio) * ib2, dbeta);
-                const R rb = -K.two_m_inv_beta * gamb;     // adjoint of a / b
-                const R ab = rb / bsum;                    // adjoint of a
-                const R bb = -rb * ratio / bsum;           // adjoint of b
-                R uxw = R(0), uyw = R(0);
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    // a = sum ds dh w, b = sum dh dh w (c enters the guard only)
-                    dsb[i] = fmaR(ab * dh[i], w[i], dsb[i]);
-                    dhb[i] = fmaR(fmaR(ab, ds[i], R(2) * bb * dh[i]), w[i], dhb[i]);
-                    const R wb = dh[i] * fmaR(ab, ds[i], bb * dh[i]);
-                    const R dbar = -wb * w[i] * w[i];       // adjoint of d_i
-                    // d_i = W_i (1 - 1.5 |u|^2 + 4.5 (c.u)^2 + 3 c.u)
-                    const R cu = R(kCx[i]) * ux + R(kCy[i]) * uy;
-                    const R wd = R(weight(i)) * dbar;
-                    uxw = fmaR(wd, fmaR(R(9) * cu, R(kCx[i]), fmaR(R(-3), ux, R(3) * R(kCx[i]))), uxw);
-                    uyw = fmaR(wd, fmaR(R(9) * cu, R(kCy[i]), fmaR(R(-3), uy, R(3) * R(kCy[i]))), uyw);
-                }
-                uxb += uxw;
-                uyb += uyw;
+        // (mul + add pairs below may fuse: nothing else is computed from
+        // these values, so there is no bitwise contract to keep)
+        {
+#pragma clang fp contract(fast)
+            // g'_i = g_i - 2 beta ds_i - beta gamma dh_i
+            R dsb[9], dhb[9];
+            R gamb = R(0), db = R(0);
+            const R tb = R(2) * K.beta, bg = K.beta * gam;
+    #pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                lam[i] = mu[i];
+                dsb[i] = -tb * mu[i];
+                dhb[i] = -bg * mu[i];
+                gamb = fmaR(mu[i], dh[i], gamb);
+                db = fmaR(mu[i], fmaR(gam, dh[i], R(2) * ds[i]), db);
             }
+            gamb = -K.beta * gamb;
+            dbeta = -db;
+            if constexpr (GM != GFIX && !FROZEN) {
+                if (active) {
+                    // gamma = 1/beta - (2 - 1/beta) a / b
+                    const R ib2 = K.inv_beta * K.inv_beta;
+                    dbeta = fmaR(gamb, -(R(1) + ratio) * ib2, dbeta);
+                    const R rb = -K.two_m_inv_beta * gamb;     // adjoint of a / b
+                    const R ab = rb * rcpR(bsum);              // adjoint of a
+                    const R bb = -ab * ratio;                  // adjoint of b = -rb a / b^2
+                    R uxw = R(0), uyw = R(0);
+    #pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        // a = sum ds dh w, b = sum dh dh w (c enters the guard only)
+                        dsb[i] = fmaR(ab * dh[i], w[i], dsb[i]);
+                        dhb[i] = fmaR(fmaR(ab, ds[i], R(2) * bb * dh[i]), w[i], dhb[i]);
+                        const R wb = dh[i] * fmaR(ab, ds[i], bb * dh[i]);
+                        const R dbar = -wb * w[i] * w[i];       // adjoint of d_i
+                        // d_i = W_i (1 - 1.5 |u|^2 + 4.5 (c.u)^2 + 3 c.u)
+                        const R cu = R(kCx[i]) * ux + R(kCy[i]) * uy;
+                        const R wd = R(weight(i)) * dbar;
+                        uxw = fmaR(wd, fmaR(R(9) * cu, R(kCx[i]), fmaR(R(-3), ux, R(3) * R(kCx[i]))), uxw);
+                        uyw = fmaR(wd, fmaR(R(9) * cu, R(kCy[i]), fmaR(R(-3), uy, R(3) * R(kCy[i]))), uyw);
+                    }
+                    uxb += uxw;
+                    uyb += uyw;
+                }
+            }
+            // ds = P(Ts, dN, dP, Qxs, Qys, As), dh = P(dT - Ts, 0, 0, dQx - Qxs, dQy - Qys, dA - As)
+            R sTb, sNb, sPb, sQxb, sQyb, sAb, hTb, hNb, hPb, hQxb, hQyb, hAb;
+            pop_to_moments_adj<R>(dsb, sTb, sNb, sPb, sQxb, sQyb, sAb);
+            pop_to_moments_adj<R>(dhb, hTb, hNb, hPb, hQxb, hQyb, hAb);
+            R dTb = hTb, dNb = sNb, dPb = sPb, dQxb = hQxb, dQyb = hQyb, dAb = hAb;
+            const R Tsb = sTb - hTb, Qxsb = sQxb - hQxb, Qysb = sQyb - hQyb, Asb = sAb - hAb;
+            if constexpr (VAR == VC) {
+                dTb += Tsb;
+            } else if constexpr (VAR == VA || VAR == VB) {
+                if constexpr (VAR == VA) dTb += Tsb + R(0.5) * (ux * Qxsb + uy * Qysb + u2 * Asb);
+                dNb += R(0.5) * (uy * Qysb - ux * Qxsb - (uxx - uyy) * Asb);
+                dPb += R(2) * (uy * Qxsb + ux * Qysb) + R(4) * ux * uy * Asb;
+                uxb += R(0.5) * (tT - dN) * Qxsb + R(2) * dP * Qysb + (R(4) * uy * dP + ux * (tT - dN)) * Asb;
+                uyb += R(2) * dP * Qxsb + R(0.5) * (tT + dN) * Qysb + (R(4) * ux * dP + uy * (tT + dN)) * Asb;
+            }
+            // dT = dPxx + dPyy, dN = dPxx - dPyy, dP = dPxy
+            const R dPxxb = dTb + dNb, dPyyb = dTb - dNb, dPxyb = dPb;
+            // moments of g - feq
+            Sxxb = dPxxb;
+            Syyb = dPyyb;
+            Sxyb = dPxyb;
+            Qxrb = dQxb;
+            Qyrb = dQyb;
+            Arb = dAb;
+            drb += -(dPxxb + dPyyb) * third - dAb * ninth;
+            jxb += -dPxxb * ux - dPxyb * uy - dQxb * third - dAb * ux * third;
+            jyb += -dPyyb * uy - dQyb * third - dAb * uy * third;
+            uxb += -dPxxb * jx - dAb * jx * third;
+            uyb += -dPyyb * jy - dPxyb * jx - dAb * jy * third;
         }
-        // ds = P(Ts, dN, dP, Qxs, Qys, As), dh = P(dT - Ts, 0, 0, dQx - Qxs, dQy - Qys, dA - As)
-        R sTb, sNb, sPb, sQxb, sQyb, sAb, hTb, hNb, hPb, hQxb, hQyb, hAb;
-        pop_to_moments_adj<R>(dsb, sTb, sNb, sPb, sQxb, sQyb, sAb);
-        pop_to_moments_adj<R>(dhb, hTb, hNb, hPb, hQxb, hQyb, hAb);
-        R dTb = hTb, dNb = sNb, dPb = sPb, dQxb = hQxb, dQyb = hQyb, dAb = hAb;
-        const R Tsb = sTb - hTb, Qxsb = sQxb - hQxb, Qysb = sQyb - hQyb, Asb = sAb - hAb;
-        if constexpr (VAR == VC) {
-            dTb += Tsb;
-        } else if constexpr (VAR == VA || VAR == VB) {
-            if constexpr (VAR == VA) dTb += Tsb + R(0.5) * (ux * Qxsb + uy * Qysb + u2 * Asb);
-            dNb += R(0.5) * (uy * Qysb - ux * Qxsb - (uxx - uyy) * Asb);
-            dPb += R(2) * (uy * Qxsb + ux * Qysb) + R(4) * ux * uy * Asb;
-            uxb += R(0.5) * (tT - dN) * Qxsb + R(2) * dP * Qysb + (R(4) * uy * dP + ux * (tT - dN)) * Asb;
-            uyb += R(2) * dP * Qxsb + R(0.5) * (tT + dN) * Qysb + (R(4) * ux * dP + uy * (tT + dN)) * Asb;
-        }
-        // dT = dPxx + dPyy, dN = dPxx - dPyy, dP = dPxy
-        const R dPxxb = dTb + dNb, dPyyb = dTb - dNb, dPxyb = dPb;
-        // moments of g - feq
-        Sxxb = dPxxb;
-        Syyb = dPyyb;
-        Sxyb = dPxyb;
-        Qxrb = dQxb;
-        Qyrb = dQyb;
-        Arb = dAb;
-        drb += -(dPxxb + dPyyb) * third - dAb * ninth;
-        jxb += -dPxxb * ux - dPxyb * uy - dQxb * third - dAb * ux * third;
-        jyb += -dPyyb * uy - dQyb * third - dAb * uy * third;
-        uxb += -dPxxb * jx - dAb * jx * third;
-        uyb += -dPyyb * jy - dPxyb * jx - dAb * jy * third;
     }
     // u = j / rho, rho = rho0 + dr
     jxb = fmaR(uxb, ir, jxb);

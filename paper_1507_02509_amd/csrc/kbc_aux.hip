@@ -2,7 +2,8 @@
 // import/export, diagnostics reductions and the bandwidth reference copy.
 //
 // All of them address the state the way the step does: the pre-collision
-// population f_i(x, t = n) sits in plane i at x - v_i.
+// population f_i(x, t = n) sits in population row i of lattice row y - v_iy,
+// at column x - v_ix ([ny][9][pitch] layout).
 #include "kbc_launch.hpp"
 
 namespace kbc {
@@ -14,7 +15,7 @@ __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >=
 // element offset of f_i(x, y) in a state buffer
 __device__ __forceinline__ int64_t src_off(int i, int x, int y, int nx, int ny, int64_t pitch) {
     const int xs = wrap(x - kCx[i], nx), ys = wrap(y - kCy[i], ny);
-    return (static_cast<int64_t>(i) * ny + ys) * pitch + xs;
+    return (static_cast<int64_t>(ys) * 9 + i) * pitch + xs;
 }
 
 // ------------------------------------------------------------ initial state
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(256) void k_init(typename Form<FORM>::S* __restrict
         const double pvv = Pxx * cx * cx + 2.0 * Pxy * cx * cy + Pyy * cy * cy;
         const double dev = weight(i) * (dr + 3.0 * r * cu + 4.5 * (r * cu * cu - r * u2 / 3.0 + pvv - tr3));
         const int xs = wrap(x - kCx[i], nx), ys = wrap(y - kCy[i], ny);
-        dst[(static_cast<int64_t>(i) * ny + ys) * pitch + xs] = F::enc64(dev, i);
+        dst[(static_cast<int64_t>(ys) * 9 + i) * pitch + xs] = F::enc64(dev, i);
     }
 }
 

@@ -81,9 +81,9 @@ int check_params(const lbm_params* p) {
 kbc::StepShape default_shape(int32_t form) {
     kbc::StepShape s;
     switch (form) {
-        case LBM_F16DEV_F32: s.width = 64; s.rpt = 4; s.nt = 1; break;
-        case LBM_F64: s.width = 256; s.rpt = 2; s.nt = 1; break;
-        default: s.width = 256; s.rpt = 2; s.nt = 0; break;
+        case LBM_F16DEV_F32: s.width = 256; s.rpt = 4; s.nt = 1; break;
+        case LBM_F64: s.width = 128; s.rpt = 1; s.nt = 1; break;
+        default: s.width = 256; s.rpt = 1; s.nt = 1; break;
     }
     return s;
 }
@@ -341,11 +341,10 @@ int lbm_adjoint_seed(lbm_ctx* c, const void* state, const double* dL_drho, const
 int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta) {
     if (!c || !state || !lam_in || !lam_out || lam_in == lam_out)
         return fail(LBM_EINVAL, "ctx, state and two distinct adjoint buffers are required");
-    const int64_t nb = kbc::adjoint_partials(c->L), ng = kbc::adjoint_folds(c->L);
+    const int64_t nb = kbc::adjoint_partials(c->L), ng = kbc::adjoint_slice_len(c->L);
     int rc = ensure_ascratch(c, static_cast<size_t>(nb + ng));
     if (rc) return rc;
-    return launch_result(kbc::launch_adjoint_step(c->L, state, lam_in, lam_out, c->ascratch,
-                                                  dbeta ? c->ascratch + nb : nullptr, dbeta),
+    return launch_result(kbc::launch_adjoint_step(c->L, state, lam_in, lam_out, c->ascratch, c->ascratch + nb, dbeta),
                          "lbm_adjoint_step");
 }
 
@@ -355,11 +354,14 @@ int lbm_adjoint_segment(lbm_ctx* c, const void* state0, void* const* slots, int3
         return fail(LBM_EINVAL, "invalid adjoint segment arguments");
     for (int32_t i = 0; i + 1 < k; ++i)
         if (!slots[i]) return fail(LBM_EINVAL, "slot %d is NULL", i);
-    // every adjoint step of the segment folds its partials into a slice of
-    // its own; one reduction at the end adds the slices, in step order, to
-    // *dbeta
-    const int64_t nb = kbc::adjoint_partials(c->L), ng = kbc::adjoint_folds(c->L);
-    int rc = ensure_ascratch(c, static_cast<size_t>(nb + ng * k));
+    // every adjoint step of the segment writes its dL/dbeta partials to a
+    // slice of its own; one reduction at the end adds the slices, in step
+    // order, to *dbeta
+    const int64_t nb = kbc::adjoint_partials(c->L), ng = kbc::adjoint_slice_len(c->L);
+    // room for k rounded up to 64 slices, so that segments of different
+    // lengths in one backward pass do not reallocate (which synchronises)
+    const int64_t kr = (static_cast<int64_t>(k) + 63) / 64 * 64;
+    int rc = ensure_ascratch(c, static_cast<size_t>(nb + ng * kr + kr));
     if (rc) return rc;
     // recompute f^{s+1} .. f^{s+k-1}
     for (int32_t i = 1; i < k; ++i) {
@@ -371,14 +373,14 @@ int lbm_adjoint_segment(lbm_ctx* c, const void* state0, void* const* slots, int3
     void* b = lam_out;
     for (int32_t n = k - 1; n >= 0; --n) {
         const void* st = (n == 0) ? state0 : slots[n - 1];
-        rc = kbc::launch_adjoint_step(c->L, st, a, b, c->ascratch,
-                                      dbeta ? c->ascratch + nb + static_cast<int64_t>(n) * ng : nullptr, nullptr);
+        rc = kbc::launch_adjoint_step(c->L, st, a, b, c->ascratch, c->ascratch + nb + static_cast<int64_t>(n) * ng,
+                                      nullptr);
         if (rc) return launch_result(rc, "lbm_adjoint_segment");
         void* t = a;
         a = b;
         b = t;
     }
-    rc = kbc::launch_sum_slices(c->ascratch + nb, ng, k, dbeta, c->L.stream);
+    rc = kbc::launch_sum_slices(c->ascratch + nb, ng, k, c->ascratch + nb + ng * kr, dbeta, c->L.stream);
     if (rc) return launch_result(rc, "lbm_adjoint_segment sum");
     *which = (a == lam_in) ? 0 : 1;
     return LBM_OK;
@@ -393,7 +395,7 @@ int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const doub
     const size_t N = static_cast<size_t>(c->p.nx) * c->p.ny;
     const size_t nb = (N + 255) / 256;
     // the adjoint step's partials and folds come first
-    const size_t off = static_cast<size_t>(kbc::adjoint_partials(c->L) + kbc::adjoint_folds(c->L));
+    const size_t off = static_cast<size_t>(kbc::adjoint_partials(c->L) + kbc::adjoint_slice_len(c->L));
     int rc = ensure_ascratch(c, off + nb + 4 * N);
     if (rc) return rc;
     return launch_result(kbc::launch_adjoint_init(c->L, rho, ux, uy, mode == LBM_INIT_GRAD_CD ? 1 : 0, lam0,
@@ -475,9 +477,6 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
             c->p.stream != m0->p.stream)
             return fail(LBM_EINVAL, "member %d differs in form, collision, variant, stabiliser or stream", r);
         if (c->p.gamma_mode == LBM_GAMMA_EXACT) return fail(LBM_EUNSUPPORTED, "exact stabiliser in an ensemble");
-        const uint64_t plane = static_cast<uint64_t>(c->p.ny) * static_cast<uint64_t>(c->L.pitch) *
-                               static_cast<uint64_t>(form_bytes(c->p.form));
-        if (plane > (uint64_t{1} << 32)) return fail(LBM_EUNSUPPORTED, "member %d: plane above 4 GiB", r);
         for (int32_t q = 0; q < r; ++q)
             if (members[q] == c) return fail(LBM_EINVAL, "member %d repeats member %d", r, q);
     }

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_ens(const EnsEntry* __restrict__ tab, i
             K.guard = static_cast<R>(e.guard);
             K.gamma_fixed = static_cast<R>(e.gamma_fixed);
             const int lt = t - e.tile_start;
-            step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT, false>(
+            step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT>(
                 static_cast<const S*>(e.buf[par]), static_cast<S*>(e.buf[par ^ 1]), e.nx, e.ny, e.pitch,
                 lt % e.ntx, lt / e.ntx, K);
         }

@@ -64,17 +64,20 @@ struct EnsLaunch {
 };
 int launch_ensemble(const Lattice& L, const EnsLaunch& a);
 
-// adjoint (kbc_adjoint.hip).  An adjoint step writes adjoint_partials(L)
-// per-workgroup dL/dbeta sums to `partials`; if `folds` is set they are folded
-// into adjoint_folds(L) sums there, and if `acc` is set as well the folds are
-// added to *acc.  launch_adjoint_init needs nblocks_cap >= ceil(nx ny / 256).
+// adjoint (kbc_adjoint.hip).  An adjoint step writes its per-workgroup
+// dL/dbeta sums as one slice of adjoint_slice_len(L) doubles to `slice`
+// (through adjoint_partials(L) doubles of scratch at `partials` on large
+// lattices, where they are folded); if `acc` is set the slice is added to
+// *acc.  launch_sum_slices adds k consecutive slices, last first, using k
+// doubles of scratch at `tot`.
+// launch_adjoint_init needs nblocks_cap >= ceil(nx ny / 256).
 int64_t adjoint_partials(const Lattice& L);
-int64_t adjoint_folds(const Lattice& L);
-int launch_sum_slices(const double* slices, int64_t ng, int k, double* acc, hipStream_t stream);
+int64_t adjoint_slice_len(const Lattice& L);
+int launch_sum_slices(const double* slices, int64_t len, int k, double* tot, double* acc, hipStream_t stream);
 int launch_adjoint_seed(const Lattice& L, const void* state, const double* drho, const double* dux,
                         const double* duy, void* lam);
 int launch_adjoint_step(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                        double* folds, double* acc);
+                        double* slice, double* acc);
 int launch_adjoint_init(const Lattice& L, const double* rho, const double* ux, const double* uy, int mode,
                         const void* lam0, double* gux, double* guy, double* P, double* partials,
                         int64_t nblocks_cap, double* acc);

@@ -1,12 +1,11 @@
 // kbc_tile.hpp -- one workgroup tile of the fused pull-stream + collide step,
 // shared by the single-lattice step kernel and the ensemble kernel.
 //
-// Addressing: the nine plane bases are uniform (scalar registers); a node's
-// loads and stores differ from them by byte offsets that fit in 32 bits when a
-// plane is below 4 GiB, so the compiler can use the scalar-base + 32-bit vector
-// offset form and skip per-access 64-bit address arithmetic.  Larger planes use
-// the same code with 64-bit offsets.  NT selects non-temporal stores (the new
-// state is not re-read before the next launch).
+// Addressing: row bases are uniform (scalar registers) and a lane adds a
+// 32-bit byte offset within the row, so loads and stores use the scalar-base +
+// vector-offset form with no per-access 64-bit address arithmetic, for any
+// lattice size.  NT selects non-temporal stores (the new state is not re-read
+// before the next launch).
 #pragma once
 
 #include <type_traits>
@@ -42,9 +41,31 @@ __device__ __forceinline__ gptr<S> uniform_ptr(S* p) {
     return reinterpret_cast<gptr<S>>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
+// Pointer to population i of row y: the state is laid out [ny][9][pitch],
+// element (i, y, x) at (9 y + i) * pitch + x.  With y uniform across the
+// wave this is a scalar base.
+template <typename S>
+__device__ __forceinline__ gptr<S> row_ptr(S* base, int y, int i, int64_t pitch) {
+    return uniform_ptr(base + (static_cast<int64_t>(y) * 9 + i) * pitch);
+}
+template <typename S>
+__device__ __forceinline__ gptr<const S> row_ptr(const S* base, int y, int i, int64_t pitch) {
+    return uniform_ptr(base + (static_cast<int64_t>(y) * 9 + i) * pitch);
+}
+
+template <typename S, typename O>
+__device__ __forceinline__ S ld_at(gptr<const S> base, O off) {
+    return *reinterpret_cast<gptr<const S>>(reinterpret_cast<__attribute__((address_space(1))) const char*>(base) +
+                                            off);
+}
+
 // Tile (tx, ty) of a lattice: 64 * TXW nodes wide, (4 / TXW) * RPT rows tall,
-// for the 256 threads of the calling workgroup.
-template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT, bool WIDE>
+// for the 256 threads of the calling workgroup.  Every wave covers 64
+// consecutive nodes of one row, so the row index is uniform across the wave:
+// the nine source rows (three y values, nine populations) and nine destination
+// rows are scalar bases, and a lane's loads and stores differ from them only
+// by the 32-bit byte offsets of x - 1, x and x + 1.
+template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
 __device__ __forceinline__ void step_tile(const typename Form<FORM>::S* __restrict__ src,
                                           typename Form<FORM>::S* __restrict__ dst, int nx, int ny,
                                           int64_t pitch, int tx, int ty,
@@ -52,56 +73,34 @@ __device__ __forceinline__ void step_tile(const typename Form<FORM>::S* __restri
     using F = Form<FORM>;
     using R = typename F::R;
     using S = typename F::S;
-    using O = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
     constexpr int TW = 64 * TXW;            // tile width
     constexpr int WR = 4 / TXW;             // wave rows per tile
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int x = tx * TW + lx;
     if (x >= nx) return;
-    const int y0 = (ty * WR + ly) * RPT;
-    const int64_t plane = static_cast<int64_t>(ny) * pitch;
-    const O rowb = static_cast<O>(pitch) * static_cast<O>(sizeof(S));
-    const O c0 = static_cast<O>(x) * sizeof(S);
-    const O cm = static_cast<O>((x == 0) ? nx - 1 : x - 1) * sizeof(S);
-    const O cp = static_cast<O>((x == nx - 1) ? 0 : x + 1) * sizeof(S);
-    // plane bases of the destination, uniform across the workgroup
-    const gptr<S> d0 = uniform_ptr(dst);
-    const gptr<S> d1 = uniform_ptr(dst + plane);
-    const gptr<S> d2 = uniform_ptr(dst + 2 * plane);
-    const gptr<S> d3 = uniform_ptr(dst + 3 * plane);
-    const gptr<S> d4 = uniform_ptr(dst + 4 * plane);
-    const gptr<S> d5 = uniform_ptr(dst + 5 * plane);
-    const gptr<S> d6 = uniform_ptr(dst + 6 * plane);
-    const gptr<S> d7 = uniform_ptr(dst + 7 * plane);
-    const gptr<S> d8 = uniform_ptr(dst + 8 * plane);
+    const int y0 = __builtin_amdgcn_readfirstlane((ty * WR + ly) * RPT);
+    const uint32_t c0 = static_cast<uint32_t>(x) * sizeof(S);
+    const uint32_t cm = static_cast<uint32_t>((x == 0) ? nx - 1 : x - 1) * sizeof(S);
+    const uint32_t cp = static_cast<uint32_t>((x == nx - 1) ? 0 : x + 1) * sizeof(S);
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int y = y0 + r;
         if (y >= ny) return;
-        const O r0 = static_cast<O>(y) * rowb;
-        const O rm = static_cast<O>((y == 0) ? ny - 1 : y - 1) * rowb;
-        const O rp = static_cast<O>((y == ny - 1) ? 0 : y + 1) * rowb;
+        const int ym = (y == 0) ? ny - 1 : y - 1;
+        const int yp = (y == ny - 1) ? 0 : y + 1;
         R g[9];
-        g[0] = F::dec(ld_at(src, r0 + c0), 0);
-        g[1] = F::dec(ld_at(src + plane, r0 + cm), 1);
-        g[2] = F::dec(ld_at(src + 2 * plane, rm + c0), 2);
-        g[3] = F::dec(ld_at(src + 3 * plane, r0 + cp), 3);
-        g[4] = F::dec(ld_at(src + 4 * plane, rp + c0), 4);
-        g[5] = F::dec(ld_at(src + 5 * plane, rm + cm), 5);
-        g[6] = F::dec(ld_at(src + 6 * plane, rm + cp), 6);
-        g[7] = F::dec(ld_at(src + 7 * plane, rp + cp), 7);
-        g[8] = F::dec(ld_at(src + 8 * plane, rp + cm), 8);
+        g[0] = F::dec(ld_at(row_ptr(src, y, 0, pitch), c0), 0);
+        g[1] = F::dec(ld_at(row_ptr(src, y, 1, pitch), cm), 1);
+        g[2] = F::dec(ld_at(row_ptr(src, ym, 2, pitch), c0), 2);
+        g[3] = F::dec(ld_at(row_ptr(src, y, 3, pitch), cp), 3);
+        g[4] = F::dec(ld_at(row_ptr(src, yp, 4, pitch), c0), 4);
+        g[5] = F::dec(ld_at(row_ptr(src, ym, 5, pitch), cm), 5);
+        g[6] = F::dec(ld_at(row_ptr(src, ym, 6, pitch), cp), 6);
+        g[7] = F::dec(ld_at(row_ptr(src, yp, 7, pitch), cp), 7);
+        g[8] = F::dec(ld_at(row_ptr(src, yp, 8, pitch), cm), 8);
         collide<R, COLL, VAR, GM>(g, K);
-        const O o = r0 + c0;
-        st_at<NT>(d0, o, F::enc(g[0], 0));
-        st_at<NT>(d1, o, F::enc(g[1], 1));
-        st_at<NT>(d2, o, F::enc(g[2], 2));
-        st_at<NT>(d3, o, F::enc(g[3], 3));
-        st_at<NT>(d4, o, F::enc(g[4], 4));
-        st_at<NT>(d5, o, F::enc(g[5], 5));
-        st_at<NT>(d6, o, F::enc(g[6], 6));
-        st_at<NT>(d7, o, F::enc(g[7], 7));
-        st_at<NT>(d8, o, F::enc(g[8], 8));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st_at<NT>(row_ptr(dst, y, i, pitch), c0, F::enc(g[i], i));
     }
 }
 

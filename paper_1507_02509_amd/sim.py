@@ -52,8 +52,10 @@ class Sim:
             raise ValueError("pitch_pad must be a multiple of 64 elements")
         self.pitch += int(pitch_pad)
         dt = _TORCH_STORE[self.form]
-        self.buf_a = torch.empty((9, self.ny, self.pitch), dtype=dt, device=self.device)
-        self.buf_b = torch.empty((9, self.ny, self.pitch), dtype=dt, device=self.device)
+        # population buffers are [ny][9][pitch]: the nine population rows of
+        # each lattice row one after another
+        self.buf_a = torch.empty((self.ny, 9, self.pitch), dtype=dt, device=self.device)
+        self.buf_b = torch.empty((self.ny, 9, self.pitch), dtype=dt, device=self.device)
         self.params = L.Params()
         self.params.nx, self.params.ny = self.nx, self.ny
         self.params.beta = float(beta)
@@ -135,7 +137,12 @@ class Sim:
         L.check(self.lib.lbm_set_adjoint_gamma(self.ctx, 1 if frozen else 0), "lbm_set_adjoint_gamma")
 
     def new_adjoint(self) -> torch.Tensor:
-        return torch.empty((9, self.ny, self.pitch), dtype=self.adjoint_dtype, device=self.device)
+        return torch.empty((self.ny, 9, self.pitch), dtype=self.adjoint_dtype, device=self.device)
+
+    def planes(self, buf: torch.Tensor) -> torch.Tensor:
+        """View of a [ny][9][pitch] state or adjoint buffer as [9][ny][nx]
+        (no copy; writes through the view change the buffer)."""
+        return buf.permute(1, 0, 2)[:, :, :self.nx]
 
     def new_state(self) -> torch.Tensor:
         return torch.empty_like(self.buf_a)

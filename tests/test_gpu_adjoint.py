@@ -47,8 +47,8 @@ def field_err(a, b):
 
 
 def to_lam(sim, lam_np):
-    lam = torch.zeros((9, sim.ny, sim.pitch), dtype=sim.adjoint_dtype, device="cuda")
-    lam[:, :, :sim.nx] = torch.from_numpy(lam_np).to(device="cuda", dtype=sim.adjoint_dtype)
+    lam = sim.new_adjoint().zero_()
+    sim.planes(lam)[...] = torch.from_numpy(lam_np).to(device="cuda", dtype=sim.adjoint_dtype)
     return lam
 
 
@@ -66,7 +66,7 @@ def test_adjoint_step_parity_f64(orc, coll, var):
     lout = s.new_adjoint()
     acc = torch.zeros(1, dtype=torch.float64, device="cuda")
     s.adjoint_step(s.state_buffer(), lin, lout, acc)
-    lg = lout[:, :, :nx].cpu().numpy()
+    lg = s.planes(lout).cpu().numpy()
     lo, dbo = orc.adjoint_step(oparams(orc, nx, ny, beta, coll, var), f0, lam_next)
     err = field_err(lg, lo)
     say("  lam err", err, "dbeta", acc.item(), dbo.sum())
@@ -90,7 +90,7 @@ def test_adjoint_step_parity_f32(orc, coll, var):
     acc = torch.zeros(1, dtype=torch.float64, device="cuda")
     s.adjoint_step(s.state_buffer(), to_lam(s, lam_next), lout, acc)
     lo, dbo = orc.adjoint_step(oparams(orc, nx, ny, beta, coll, var), f0r, lam_next)
-    err = field_err(lout[:, :, :nx].cpu().numpy(), lo)
+    err = field_err(s.planes(lout).cpu().numpy(), lo)
     say("  f32 lam err", err, "dbeta", acc.item(), dbo.sum())
     # FP32 bound: the derivative of gamma* carries 1 / <dh|dh>, which
     # amplifies the binary32 rounding of the state
@@ -290,4 +290,4 @@ def test_seed_matches_loss_derivative(orc):
     s.adjoint_seed(s.state_buffer(), lam, a, bx, by)
     rho, ux, uy = orc.moments(oparams(orc, nx, ny, beta, "kbc", "B"), f0)
     want = a[None] + (bx[None] * (VEL[:, 0, None, None] - ux[None]) + by[None] * (VEL[:, 1, None, None] - uy[None])) / rho[None]
-    assert field_err(lam[:, :, :nx].cpu().numpy(), want) < 1e-13
+    assert field_err(s.planes(lam).cpu().numpy(), want) < 1e-13
