@@ -34,19 +34,21 @@ METRIC = "MLUPS and % of HBM roofline (KBC fwd, adjoint) at stated error vs FP64
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f16": 36, "f32": 72, "f64": 144}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
-STEP_SOURCES = [os.path.join(ROOT, "paper_1507_02509_amd", "csrc", f)
-                for f in ("kbc_step.hip", "kbc_tile.hpp", "kbc_device.hpp")]
+_CSRC = os.path.join(ROOT, "paper_1507_02509_amd", "csrc")
+STEP_SOURCES = [os.path.join(_CSRC, f) for f in ("kbc_step.hip", "kbc_tile.hpp", "kbc_device.hpp")]
+ADJOINT_SOURCES = [os.path.join(_CSRC, f)
+                   for f in ("kbc_adjoint.hip", "kbc_adjoint.hpp", "kbc_tile.hpp", "kbc_device.hpp")]
 
 
-def kernel_digest() -> str:
+def kernel_digest(sources=STEP_SOURCES) -> str:
     h = hashlib.sha256()
-    for p in STEP_SOURCES:
+    for p in sources:
         with open(p, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key: str):
+def measured_traffic(key: str, section: str = "step"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source."""
     try:
@@ -54,7 +56,9 @@ def measured_traffic(key: str):
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_digest") != kernel_digest():
+    rec = rec.get(section, {})
+    sources = STEP_SOURCES if section == "step" else ADJOINT_SOURCES
+    if rec.get("kernel_digest") != kernel_digest(sources):
         return None
     entry = rec.get("workloads", {}).get(key)
     return None if entry is None else entry.get("bytes_per_launch")
@@ -315,7 +319,8 @@ def main():
         extras["adjoint_f32"] = {"mlups": round(nodes / (ams * 1e-3) / 1e6, 1), "ms_per_step": round(ams, 4),
                                  "bytes_per_node": 108,
                                  "hbm_frac": round(108 * nodes / (ams * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                 "adjoint_over_forward_kernel": round(ams / ms, 3)}
+                                 "adjoint_over_forward_kernel": round(ams / ms, 3),
+                                 "traffic": measured_traffic(f"adjoint_f32_kbcB_{n}", section="adjoint")}
     if "rollout" in want:
         progress("rollout 512^2 x 2000")
         extras["rollout_512_2000_f32"] = time_c5(dev)
