@@ -1,0 +1,101 @@
+"""Parity at the full roofline size: the 16384^2 decaying-turbulence lattice
+(k0 = 32, u_rms = 0.05, nu = 1e-4, seed 3, Grad initialisation with central
+differences, KBC-B), stepped on the GPU in the launch configuration the
+benchmark times (the default tile of each storage form), checked against the
+oracle on sampled nodes.
+
+The oracle cannot hold this lattice, but one step at a node depends only on a
+5 x 5 patch of the initial velocity: f^1_i(x) is component i of the collision
+at the source node x - v_i, whose Grad populations need u there and at its
+four neighbours (central differences).  So for every sampled node the oracle
+builds the nine source nodes' populations (node_grad) and collides them
+(node_collide), and the GPU's f^1 at that node must match.  Samples include
+the four corners and the edges, where the periodic wrap is taken, and nodes on
+tile edges.
+
+Tolerances (max |gpu - oracle| / max |oracle - W| over the samples): FP64
+1e-12, FP32 2e-5, FP16 5e-3, as for one step on the small lattices.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1507_02509_amd import inputs
+from paper_1507_02509_amd.sim import Sim, beta_from_nu
+
+pytestmark = pytest.mark.gpu
+
+N, K0, URMS, NU, SEED = 16384, 32, 0.05, 1e-4, 3
+W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+TOL = {"f64": 1e-12, "f32": 2e-5, "f16": 5e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def field():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("full-size field", N, "k0", K0, "seed", SEED)
+    ux, uy = inputs.spectral(N, K0, URMS, seed=SEED, device="cuda")
+    return ux, uy
+
+
+def sample_nodes():
+    rng = np.random.default_rng(11)
+    pts = [(0, 0), (N - 1, 0), (0, N - 1), (N - 1, N - 1), (0, N // 2), (N // 2, 0), (N - 1, N // 3),
+           (N // 3, N - 1), (255, 77), (256, 77), (127, 4095), (128, 4096)]
+    pts += [tuple(int(v) for v in rng.integers(0, N, 2)) for _ in range(40)]
+    return pts
+
+
+def oracle_f1(orc, ux, uy, beta, x, y):
+    """f^1 at (x, y) from the oracle's node functions."""
+    dx = np.arange(-2, 3)
+    ys = (y + dx) % N
+    xs = (x + dx) % N
+    # 5 x 5 velocity patch around (x, y), patch[j, i] = u(x + i - 2, y + j - 2)
+    iy = torch.as_tensor(ys, device=ux.device)[:, None]
+    ix = torch.as_tensor(xs, device=ux.device)[None, :]
+    pu = ux[iy, ix].cpu().numpy()
+    pv = uy[iy, ix].cpu().numpy()
+    p = orc.Params(N, N, beta, collision=orc.KBC, variant=orc.VARIANTS["B"])
+    out = np.zeros(9)
+    for i in range(9):
+        # source node x - v_i, at patch index (2 - c_y, 2 - c_x)
+        j, k = 2 - CY[i], 2 - CX[i]
+        du = [0.5 * (pu[j, k + 1] - pu[j, k - 1]), 0.5 * (pu[j + 1, k] - pu[j - 1, k]),
+              0.5 * (pv[j, k + 1] - pv[j, k - 1]), 0.5 * (pv[j + 1, k] - pv[j - 1, k])]
+        f0 = orc.node_grad(1.0, pu[j, k], pv[j, k], du, beta)
+        post, _ = orc.node_collide(p, f0)
+        out[i] = post[i]
+    return out
+
+
+@pytest.mark.parametrize("form", ["f32", "f64", "f16"])
+def test_fullsize_one_step_sampled(orc, field, form):
+    ux, uy = field
+    beta = beta_from_nu(NU)
+    say("full-size one step", form)
+    s = Sim(N, N, beta, collision="kbc", variant="B", form=form).init(ux, uy)
+    s.step(1)
+    torch.cuda.synchronize()
+    pts = sample_nodes()
+    xs = torch.as_tensor([p[0] for p in pts], device="cuda")
+    ys = torch.as_tensor([p[1] for p in pts], device="cuda")
+    f = s.get_populations()
+    fg = f[:, ys, xs].cpu().numpy().T          # [samples, 9]
+    del f, s
+    torch.cuda.empty_cache()
+    fo = np.array([oracle_f1(orc, ux, uy, beta, x, y) for x, y in pts])
+    err = np.abs(fg - fo).max() / np.abs(fo - W).max()
+    say("  samples", len(pts), "err", err)
+    assert np.isfinite(fg).all()
+    assert err < TOL[form]
