@@ -195,7 +195,7 @@ def form_errors(n, nu, seed, k0, dev, steps=10):
     return {"steps": steps, "u_rel_err_vs_f64": res}
 
 
-def cpu_baseline(n: int, nu: float, seed: int, k0: float, target_s: float = 12.0):
+def cpu_baseline(n: int, nu: float, seed: int, k0: float, target_s: float = 16.0):
     """The FP64 oracle (unmodified) on a 2048-row slab of the same workload,
     treated as a periodic 16384 x 2048 lattice (the same per-node work)."""
     import oracle
@@ -257,6 +257,7 @@ def main():
 
     progress(f"init {n}x{n} {args.form} KBC-{args.variant}")
     sim = make_sim(n, args.form, "kbc", args.variant, nu, seed, k0, dev)
+    d0 = sim.diagnostics()
     ms, wall = time_steps(sim, args.steps, args.warmup)
     progress(f"timed {args.steps} steps: {ms:.4f} ms/step")
     d = sim.diagnostics()
@@ -352,7 +353,9 @@ def main():
                      "kernel": f"k_step<{args.form},KBC-{args.variant}>",
                      "algorithmic_bytes_per_launch": BYTES_PER_NODE[args.form] * nodes},
         "wall_s_timed": round(wall, 3),
-        "final_state": {"mass_drift_rel": None, "E": d["E"], "Z": d["Z"], "gamma_mean": d["gamma"],
+        "final_state": {"steps": args.warmup + args.steps,
+                        "mass_drift_rel": (d["mass"] - d0["mass"]) / d0["mass"],
+                        "E": d["E"], "Z": d["Z"], "gamma_mean": d["gamma"],
                         "n_nonfinite": d["n_nonfinite"]},
         "extras": extras,
     }
