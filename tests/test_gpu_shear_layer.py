@@ -1,0 +1,107 @@
+"""The doubly periodic shear layer (section "Doubly Periodic Shear Layer") on
+the GPU against the oracle.
+
+Set-up of the paper's under-resolved case: N = 128, kappa = 80, u0 = 0.04,
+Re = u0 N / nu = 30000, perturbation delta = 0.05 (the paper does not state
+delta), Grad initialisation with unit density; turnover time t_c = N / u0 =
+3200 steps.
+
+* FP64, every collision: rho, u_x and u_y after 400 steps match the oracle
+  (max |diff| / max |field| per field) to 1e-10, or to 100 times the
+  oracle's own sensitivity where that is larger: the run repeated from the
+  oracle's initial state perturbed by 1e-15 relative shows how far rounding
+  differences alone carry.  The plateaus of the layer sit close to
+  equilibrium, where gamma* of models A and C projects ds onto a nearly
+  vanishing dh and amplifies such differences (measured: about 2e-3 for A
+  and 2e-5 for C after 400 steps); B, D and LBGK stay near 1e-11.
+* KBC-B at t = t_c: energy and enstrophy of the FP64 form match the oracle's
+  to 1e-9 relative; the FP32 form to 1e-3 (energy) and 1e-2 (enstrophy),
+  the proposed trace bounds for chaotic runs.
+* Every KBC variant stays finite to t_c at this resolution, where the paper
+  reports KBC runs throughout; LBGK is run and reported, not asserted.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1507_02509_amd import inputs
+from paper_1507_02509_amd.sim import Sim
+
+pytestmark = pytest.mark.gpu
+
+N, KAPPA, U0, RE, DELTA = 128, 80.0, 0.04, 30000.0, 0.05
+NU = U0 * N / RE
+BETA = 1.0 / (6.0 * NU + 1.0)
+TC = int(round(N / U0))
+CASES = [("lbgk", "A"), ("kbc", "A"), ("kbc", "B"), ("kbc", "C"), ("kbc", "D")]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def layer():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return inputs.shear_layer(N, U0, KAPPA, DELTA)
+
+
+def oparams(orc, coll, var, threads=16):
+    return orc.Params(N, N, BETA, collision=orc.LBGK if coll == "lbgk" else orc.KBC,
+                      variant=orc.VARIANTS[var], threads=threads)
+
+
+def field_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("coll,var", CASES)
+def test_shear_layer_fp64_400_steps(orc, layer, coll, var):
+    ux, uy = layer
+    say("shear layer f64", coll, var)
+    s = Sim(N, N, BETA, collision=coll, variant=var, form="f64").init(ux, uy)
+    s.step(400)
+    rho, gx, gy = (t.cpu().numpy() for t in s.moments())
+    p = oparams(orc, coll, var)
+    f0 = orc.init(p, ux, uy)
+    orho, ox, oy = orc.moments(p, orc.run(p, f0, 400))
+    errs = (field_err(rho, orho), field_err(gx, ox), field_err(gy, oy))
+    rng = np.random.default_rng(0)
+    prho, px, py = orc.moments(p, orc.run(p, f0 * (1 + 1e-15 * rng.standard_normal(f0.shape)), 400))
+    sens = max(field_err(prho, orho), field_err(px, ox), field_err(py, oy))
+    bar = max(1e-10, 100 * sens)
+    say("  errors rho, ux, uy:", errs, "oracle self-sensitivity", sens, "bar", bar)
+    assert max(errs) < bar
+
+
+def test_shear_layer_kbc_b_to_turnover(orc, layer):
+    ux, uy = layer
+    p = oparams(orc, "kbc", "B")
+    fo = orc.run(p, orc.init(p, ux, uy), TC)
+    do = orc.diagnostics(p, fo)
+    for form, bE, bZ in (("f64", 1e-9, 1e-9), ("f32", 1e-3, 1e-2)):
+        s = Sim(N, N, BETA, collision="kbc", variant="B", form=form).init(ux, uy)
+        s.step(TC)
+        d = s.diagnostics()
+        eE = abs(d["E"] - do["E"]) / do["E"]
+        eZ = abs(d["Z"] - do["Z"]) / do["Z"]
+        say(f"  t_c = {TC}: {form} E {d['E']:.6e} (oracle {do['E']:.6e}, rel {eE:.2e}), "
+            f"Z {d['Z']:.6e} (oracle {do['Z']:.6e}, rel {eZ:.2e})")
+        assert d["n_nonfinite"] == 0
+        assert eE < bE and eZ < bZ
+
+
+@pytest.mark.parametrize("coll,var", CASES)
+def test_shear_layer_stability_fp32(layer, coll, var):
+    ux, uy = layer
+    s = Sim(N, N, BETA, collision=coll, variant=var, form="f32").init(ux, uy)
+    s.step(TC)
+    d = s.diagnostics()
+    say(f"  {coll}-{var} f32 at t_c: nonfinite {d['n_nonfinite']}, E {d['E']:.4e}, Z {d['Z']:.4e}")
+    if coll == "kbc":
+        assert d["n_nonfinite"] == 0
