@@ -35,7 +35,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f16": 36, "f32": 72, "f64": 144}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 _CSRC = os.path.join(ROOT, "paper_1507_02509_amd", "csrc")
-STEP_SOURCES = [os.path.join(_CSRC, f) for f in ("kbc_step.hip", "kbc_tile.hpp", "kbc_device.hpp")]
+STEP_SOURCES = [os.path.join(_CSRC, f) for f in ("kbc_step.hip", "kbc_step2.hip", "kbc_tile.hpp", "kbc_device.hpp")]
+# FP arithmetic operations of one KBC-B collision per node (adds, multiplies,
+# reciprocals and conversions count one, FMAs two), counted in the gfx950 code
+# of the single-step kernel; the vector peaks are MI355X's published ones
+FLOPS_PER_NODE_STEP = {"f32": 282, "f16": 302, "f64": 389}
+VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f16": 157.3, "f64": 78.6}
 ADJOINT_SOURCES = [os.path.join(_CSRC, f)
                    for f in ("kbc_adjoint.hip", "kbc_adjoint.hpp", "kbc_tile.hpp", "kbc_device.hpp")]
 
@@ -235,6 +240,8 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--form", default="f32", choices=["f16", "f32", "f64"])
     ap.add_argument("--variant", default="B")
+    ap.add_argument("--fusion", type=lambda v: tuple(int(x) for x in v.split(",")), default=None,
+                    help="steps per launch [,fused tile rows], e.g. 1 or 2,16 (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default="forms,lbgk,copy,adjoint,rollout,ensemble,accuracy",
@@ -257,6 +264,10 @@ def main():
 
     progress(f"init {n}x{n} {args.form} KBC-{args.variant}")
     sim = make_sim(n, args.form, "kbc", args.variant, nu, seed, k0, dev)
+    if args.fusion is not None:
+        sim.set_fusion(*args.fusion)
+    spl = sim.fusion
+    rows = sim.fusion_rows
     d0 = sim.diagnostics()
     ms, wall = time_steps(sim, args.steps, args.warmup)
     progress(f"timed {args.steps} steps: {ms:.4f} ms/step")
@@ -265,9 +276,30 @@ def main():
     torch.cuda.empty_cache()
     nodes = n * n
     mlups = nodes / (ms * 1e-3) / 1e6
-    achieved = BYTES_PER_NODE[args.form] * nodes / (ms * 1e-3) / 1e9
-    key = f"{args.form}_kbc{args.variant}_{n}"
+    launch_ms = ms * spl      # one launch advances spl steps (an odd step count adds one single step)
+    bytes_launch = BYTES_PER_NODE[args.form] * nodes      # state read + written once per launch
+    hbm_gbs = bytes_launch / (launch_ms * 1e-3) / 1e9
+    key = f"{args.form}_kbc{args.variant}_{n}" + ("_fused2" if spl == 2 else "")
     traffic = measured_traffic(key)
+    kname = (f"k_step2<{args.form},KBC-{args.variant},64x{rows}>" if spl == 2
+             else f"k_step<{args.form},KBC-{args.variant}>")
+    if spl == 2 and args.variant == "B":
+        # two steps per pass through HBM: the kernel is bound by vector
+        # arithmetic, not by HBM
+        flops_launch = FLOPS_PER_NODE_STEP[args.form] * nodes * spl
+        achieved = flops_launch / (launch_ms * 1e-3) / 1e12
+        peak = VECTOR_PEAK_TFLOPS[args.form]
+        roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kname,
+                    "steps_per_launch": spl, "algorithmic_flops_per_launch": flops_launch,
+                    "algorithmic_bytes_per_launch": bytes_launch, "hbm_GBs": round(hbm_gbs, 1),
+                    "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                    "single_pass_hbm_frac": round(BYTES_PER_NODE[args.form] * nodes / (ms * 1e-3) / 1e9
+                                                  / HBM_PEAK_GBS, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                    "steps_per_launch": spl, "algorithmic_bytes_per_launch": bytes_launch}
 
     extras = {}
     want = set() if args.no_extras else set(args.extras.split(","))
@@ -348,10 +380,7 @@ def main():
         "config": {"workload": workload, "nx": n, "ny": n, "collision": f"KBC-{args.variant}",
                    "form": f"{args.form}dev" if args.form != "f64" else "f64", "nu": nu, "seed": seed,
                    "k0": k0, "u_rms": 0.05, "init": "grad_cd"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": f"k_step<{args.form},KBC-{args.variant}>",
-                     "algorithmic_bytes_per_launch": BYTES_PER_NODE[args.form] * nodes},
+        "roofline": roofline,
         "wall_s_timed": round(wall, 3),
         "final_state": {"steps": args.warmup + args.steps,
                         "mass_drift_rel": (d["mass"] - d0["mass"]) / d0["mass"],

@@ -161,6 +161,21 @@ void* lbm_work_buffer(const lbm_ctx* c);
 #define LBM_TILE_NONTEMPORAL 1
 int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t flags);
 
+/* Time steps per kernel launch in lbm_step: 1, or 2 (temporal blocking: each
+ * workgroup runs the first step on its 64 x `rows` tile plus a one-node ring,
+ * keeps that state in LDS and runs the second step from it, so a pair of
+ * steps reads and writes the state once).  `rows` in {8, 16, 24, 32} sets the
+ * fused tile height (0 keeps the current one; 32 is LBM_EUNSUPPORTED for
+ * FP64, whose tile would not fit the LDS of a CU).  Defaults: 2 steps with 16
+ * rows for FP32, 2 steps with 8 rows for FP64, 1 step for FP16.  Odd
+ * remainders run as single steps.  Results are bitwise identical for every
+ * setting; the non-temporal flag of lbm_set_tile applies to the fused launch
+ * too.  LBM_EINVAL for other values.  lbm_get_fusion returns the steps per
+ * launch and stores the fused tile height in *rows when rows is not NULL
+ * (-1 for a NULL ctx). */
+int lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows);
+int lbm_get_fusion(const lbm_ctx* c, int32_t* rows);
+
 /* Replace beta (e.g. between rollouts); other parameters are fixed per ctx. */
 int lbm_set_beta(lbm_ctx* c, double beta);
 

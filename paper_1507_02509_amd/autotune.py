@@ -1,9 +1,12 @@
 """Tile-shape autotuner for the step and ensemble kernels.
 
-It times every candidate tile (width, rows per thread, non-temporal stores)
-on the caller's own lattice or ensemble with HIP events, keeps the one with
-the smallest median time, and caches the choice in a JSON file keyed by the
-device name and the configuration (form, collision, variant, lattice sizes).
+For a single lattice it times every candidate launch configuration -- the
+single-step kernel with each tile (width, rows per thread, non-temporal
+stores) and the two-step fused kernel with each tile height and store kind --
+on the caller's own lattice with HIP events; for an ensemble, every tile of
+the ensemble kernel.  It keeps the one with the smallest median time and
+caches the choice in a JSON file keyed by the device name and the
+configuration (form, collision, variant, lattice sizes).
 The lattice state is restored afterwards: every trial takes an even number of
 steps and the state buffers are copied back, so tuning changes nothing but
 the tile.  Results of the step kernels are bitwise identical for every tile,
@@ -17,9 +20,25 @@ import os
 
 import torch
 
+from . import _lib
+
 STEP_TILES = [(w, r, nt) for (w, r) in ((64, 1), (64, 4), (128, 1), (128, 2), (128, 4), (256, 1), (256, 2))
               for nt in (False, True)]
 ENSEMBLE_TILES = [(w, r, nt) for (w, r) in ((128, 2), (256, 1), (256, 2)) for nt in (False, True)]
+# launch configurations of a single lattice: ("single", width, rows per
+# thread, nt) or ("fused", tile rows, nt) (two steps per launch)
+STEP_CANDIDATES = ([("single",) + t for t in STEP_TILES] +
+                   [("fused", rows, nt) for rows in (8, 16, 24, 32) for nt in (False, True)])
+
+
+def apply_config(sim, cand):
+    """Set a launch configuration from STEP_CANDIDATES on a Sim."""
+    if cand[0] == "single":
+        sim.set_fusion(1)
+        sim.set_tile(*cand[1:])
+    else:
+        sim.set_fusion(2, cand[1])   # raises for a 32-row FP64 tile (skipped by the tuner)
+        sim.set_tile(256, 1, cand[2])   # the tile of an odd remaining single step
 
 
 def cache_path() -> str:
@@ -64,25 +83,28 @@ def _sim_key(sim) -> str:
 
 
 def tune_sim(sim, steps: int = 10, reps: int = 3, candidates=None, use_cache: bool = True):
-    """Choose and apply the fastest step tile for this lattice; returns
-    (width, rows_per_thread, nontemporal) and the per-candidate timings."""
+    """Choose and apply the fastest launch configuration for this lattice;
+    returns the chosen entry of STEP_CANDIDATES and the per-candidate
+    timings."""
     path = cache_path()
     key = _sim_key(sim)
     cache = _load(path) if use_cache else {}
     if use_cache and key in cache:
         best = tuple(cache[key]["tile"])
-        sim.set_tile(*best)
+        apply_config(sim, best)
         return best, cache[key].get("ms", {})
     steps += steps % 2
     snap = sim.state_buffer().clone()
     n0 = sim.steps
     timings = {}
-    for cand in candidates or STEP_TILES:
-        sim.set_tile(*cand)
+    for cand in candidates or STEP_CANDIDATES:
+        if cand[0] == "fused" and cand[1] == 32 and sim.form == _lib.F64:
+            continue
+        apply_config(sim, cand)
         sim.step(2)
         timings[cand] = _time(sim.step, steps, reps)
     best = min(timings, key=timings.get)
-    sim.set_tile(*best)
+    apply_config(sim, best)
     sim.state_buffer().copy_(snap)
     sim.lib.lbm_set_step(sim.ctx, n0)
     torch.cuda.synchronize()

@@ -29,6 +29,9 @@ struct StepShape {
 bool valid_shape(const StepShape& s);
 
 int launch_step(const Lattice& L, const void* src, void* dst, const StepShape& shape);
+// two fused steps src -> dst (kbc_step2.hip): output tiles of 64 x rows
+// nodes, rows in {8, 16, 24, 32} (32 not for FP64); nt: non-temporal stores
+int launch_step2(const Lattice& L, const void* src, void* dst, int rows, int nt);
 int launch_init(const Lattice& L, void* dst, const double* rho, const double* ux, const double* uy,
                 const double* grad, int mode);
 int launch_moments(const Lattice& L, const void* src, double* rho, double* ux, double* uy,

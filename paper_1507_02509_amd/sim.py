@@ -40,7 +40,7 @@ class Sim:
     def __init__(self, nx: int, ny: int, beta: float, collision: str = "kbc", variant: str = "B",
                  form: str = "f32", gamma_mode: str = "estimate", gamma_guard: float = 1e-12,
                  gamma_fixed: float = 2.0, rho0: float = 1.0, device="cuda:0", tile: tuple | None = None,
-                 pitch_pad: int = 0):
+                 pitch_pad: int = 0, fusion: int | None = None):
         self.lib = L.load()
         self.device = torch.device(device)
         self.nx, self.ny = int(nx), int(ny)
@@ -69,6 +69,7 @@ class Sim:
         self.params.stream = torch.cuda.current_stream(self.device).cuda_stream
         self.ctx = ctypes.c_void_p()
         self._tile = tile
+        self._fusion = fusion
         self._inputs = None
 
     # ------------------------------------------------------------------ setup
@@ -85,7 +86,28 @@ class Sim:
         self._inputs = (ux, uy, rho, grad)   # alive until the init kernel has run
         if self._tile is not None:
             self.set_tile(*self._tile)
+        if self._fusion is not None:
+            self.set_fusion(*(self._fusion if isinstance(self._fusion, tuple) else (self._fusion,)))
         return self
+
+    def set_fusion(self, steps_per_launch: int, rows: int = 0):
+        """Time steps per kernel launch (1, or 2 = two fused steps) and the
+        fused tile height (8, 16, 24 or 32 rows; 0 keeps the current one)."""
+        self._fusion = (int(steps_per_launch), int(rows))
+        if self.ctx:
+            L.check(self.lib.lbm_set_fusion(self.ctx, *self._fusion), "lbm_set_fusion")
+
+    @property
+    def fusion(self) -> int:
+        """Time steps per kernel launch."""
+        return int(self.lib.lbm_get_fusion(self.ctx, None))
+
+    @property
+    def fusion_rows(self) -> int:
+        """Output tile height of the fused launch."""
+        r = ctypes.c_int32(0)
+        self.lib.lbm_get_fusion(self.ctx, ctypes.byref(r))
+        return int(r.value)
 
     def set_tile(self, width: int, rows_per_thread: int = 1, nontemporal: bool = False):
         L.check(self.lib.lbm_set_tile(self.ctx, int(width), int(rows_per_thread), 1 if nontemporal else 0),

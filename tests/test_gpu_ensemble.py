@@ -138,7 +138,7 @@ def test_autotuner_restores_state_and_caches(tmp_path, monkeypatch):
     before = s.planes(s.state_buffer()).clone()
     n0 = s.steps
     best, timings = autotune.tune_sim(s, steps=4, reps=1)
-    assert best in autotune.STEP_TILES and len(timings) == len(autotune.STEP_TILES)
+    assert best in autotune.STEP_CANDIDATES and len(timings) == len(autotune.STEP_CANDIDATES)
     assert torch.equal(s.planes(s.state_buffer()), before) and s.steps == n0
     again, _ = autotune.tune_sim(s)
     assert again == best
