@@ -309,19 +309,23 @@ def main():
             if form == args.form or "forms" not in want:
                 continue
             s = make_sim(n, form, "kbc", args.variant, nu, seed, k0, dev)
+            fs = s.fusion
             m, _ = time_steps(s, args.extra_steps, 2)
             progress(f"{form}: {m:.4f} ms/step")
             del s
             torch.cuda.empty_cache()
+            # HBM moves the state once per launch of fs steps
             extras[f"kbc{args.variant}_{form}"] = {
-                "mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4),
-                "hbm_frac": round(BYTES_PER_NODE[form] * nodes / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4), "steps_per_launch": fs,
+                "hbm_frac": round(BYTES_PER_NODE[form] * nodes / (fs * m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if "lbgk" in want:
         s = make_sim(n, args.form, "lbgk", "A", nu, seed, k0, dev)
+        fs = s.fusion
         m, _ = time_steps(s, args.extra_steps, 2)
         del s
         torch.cuda.empty_cache()
-        extras[f"lbgk_{args.form}"] = {"mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4)}
+        extras[f"lbgk_{args.form}"] = {"mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4),
+                                       "steps_per_launch": fs}
         extras["kbc_over_lbgk_time"] = round(ms / m, 3)
     if "copy" in want:
         # the copy reference: 2 x 1.2 GB read + write
@@ -352,7 +356,7 @@ def main():
         extras["adjoint_f32"] = {"mlups": round(nodes / (ams * 1e-3) / 1e6, 1), "ms_per_step": round(ams, 4),
                                  "bytes_per_node": 108,
                                  "hbm_frac": round(108 * nodes / (ams * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                 "adjoint_over_forward_kernel": round(ams / ms, 3),
+                                 "adjoint_over_forward_step": round(ams / ms, 3),
                                  "traffic": measured_traffic(f"adjoint_f32_kbcB_{n}", section="adjoint")}
     if "rollout" in want:
         progress("rollout 512^2 x 2000")
