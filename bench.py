@@ -244,7 +244,7 @@ def main():
                     help="steps per launch [,fused tile rows], e.g. 1 or 2,16 (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="forms,lbgk,copy,adjoint,rollout,ensemble,accuracy",
+    ap.add_argument("--extras", default="forms,lbgk,exact,copy,adjoint,rollout,ensemble,accuracy",
                     help="comma-separated extra measurements")
     ap.add_argument("--extra-steps", type=int, default=50,
                     help="timed steps for the other forms and the LBGK baseline")
@@ -318,6 +318,23 @@ def main():
             extras[f"kbc{args.variant}_{form}"] = {
                 "mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4), "steps_per_launch": fs,
                 "hbm_frac": round(BYTES_PER_NODE[form] * nodes / (fs * m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if "exact" in want:
+        # the exact stabiliser: per-node Newton root of the entropy condition
+        from paper_1507_02509_amd import inputs
+        from paper_1507_02509_amd.sim import Sim, beta_from_nu
+        ux, uy = inputs.spectral(n, k0, 0.05, seed=seed, device=dev)
+        s = Sim(n, n, beta_from_nu(nu), collision="kbc", variant=args.variant, form=args.form,
+                gamma_mode="exact", device=dev).init(ux, uy)
+        del ux, uy
+        fs = s.fusion
+        m, _ = time_steps(s, args.extra_steps, 2)
+        progress(f"exact stabiliser: {m:.4f} ms/step")
+        d = s.diagnostics()
+        del s
+        torch.cuda.empty_cache()
+        extras[f"kbc{args.variant}_{args.form}_exact_gamma"] = {
+            "mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4), "steps_per_launch": fs,
+            "over_estimate_time": round(m / ms, 3), "gamma_mean": d["gamma"]}
     if "lbgk" in want:
         s = make_sim(n, args.form, "lbgk", "A", nu, seed, k0, dev)
         fs = s.fusion

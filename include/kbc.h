@@ -70,7 +70,13 @@ typedef enum { LBM_KBC_A = 0, LBM_KBC_B = 1, LBM_KBC_C = 2, LBM_KBC_D = 3 } lbm_
 typedef enum { LBM_F16DEV_F32 = 0, LBM_F32DEV_F32 = 1, LBM_F64 = 2 } lbm_form;
 /* stabiliser: gamma* of eq. (result21) with the denominator guard, a fixed
  * value (gamma_fixed; 2 gives LBGK, 1/beta the regularised model), or the
- * root of eq. (result1) by Newton iteration from gamma* */
+ * root of eq. (result1) by Newton iteration from gamma* (guarded nodes keep
+ * gamma = 2; the iteration stops when a logarithm's argument would leave
+ * (0, inf), after a step below 1e-15 (FP64) or 5e-7 (FP32 arithmetic)
+ * relative, after a step that is not at most half the previous one (rounding
+ * noise reached), or after 100 / 20 steps).  LBM_GAMMA_EXACT runs in the step,
+ * moments and diagnostics; the adjoint and the ensemble return
+ * LBM_EUNSUPPORTED for it. */
 typedef enum { LBM_GAMMA_ESTIMATE = 0, LBM_GAMMA_FIXED = 1, LBM_GAMMA_EXACT = 2 } lbm_gamma_mode;
 /* initial populations: equilibrium eq. (Eq); Grad's approximation eq. (Grad)
  * with Pi = Pi^eq + Pi^(1) (eqs. Peq, P1AC) and velocity gradients from

@@ -277,6 +277,14 @@ template <int FORM, int COLL, int VAR, int GM>
 struct AdjStepOp {
     static int run(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
                    double* slice, double* acc) {
+        if constexpr (GM == GEXACT) {
+            return -5;   // the adjoint of the exact stabiliser is not built
+        } else {
+            return go(L, state, lin, lout, partials, slice, acc);
+        }
+    }
+    static int go(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
+                  double* slice, double* acc) {
         using F = Form<FORM>;
         using R = typename F::R;
         const int ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;

@@ -73,8 +73,6 @@ int check_params(const lbm_params* p) {
         return fail(LBM_EINVAL, "unknown gamma_mode %d", p->gamma_mode);
     if (!(p->gamma_guard >= 0.0) || !isfinite(p->gamma_guard)) return fail(LBM_EINVAL, "gamma_guard must be finite and >= 0");
     if (p->gamma_mode == LBM_GAMMA_FIXED && !isfinite(p->gamma_fixed)) return fail(LBM_EINVAL, "gamma_fixed must be finite");
-    if (p->collision == LBM_KBC && p->gamma_mode == LBM_GAMMA_EXACT)
-        return fail(LBM_EUNSUPPORTED, "LBM_GAMMA_EXACT is not built in this library");
     return LBM_OK;
 }
 

@@ -116,6 +116,55 @@ __device__ __forceinline__ void moments_to_pop(R T, R N, R P, R Qx, R Qy, R A, R
     p[8] = q * (am + (Qx - Qy));
 }
 
+// Root of the entropy-maximum condition eq. (result1) in gamma,
+//   F(gamma) = sum_i dh_i ln(1 + x_i) = 0,
+//   x_i = ((1 - beta gamma) dh_i - (2 beta - 1) ds_i) / feq_i,
+// by Newton's method from gamma* (its first-order root, eq. (result21)).
+// F decreases strictly in gamma while every 1 + x_i > 0, so the root is
+// unique; the iteration stops (keeping the current gamma) if an argument of
+// the logarithm leaves (0, inf) or F' is not negative, after a step below
+// the tolerance of the arithmetic type, after a step that is not at most half
+// the previous one (Newton's steps shrink quadratically until rounding noise
+// in F takes over, which at a near-equilibrium node lies above the FP32
+// tolerance), or after a fixed number of steps.
+// 1 / feq_i = w_i / rho with w_i = 1 / (W_i (1 + e_i)); ln(1 + x) is taken
+// as log1p(x), exact to rounding for the small x of a near-equilibrium node.
+template <typename R>
+__device__ __forceinline__ R exact_gamma(R gam, const R (&ds)[9], const R (&dh)[9], const R (&w)[9], R ir,
+                                         const Coef<R>& K) {
+    constexpr int kMaxIt = sizeof(R) == 8 ? 100 : 20;
+    const R tol = sizeof(R) == 8 ? R(1e-15) : R(5e-7);
+    const R tbm1 = R(2) * K.beta - R(1);
+    R wr[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) wr[i] = w[i] * ir;
+    R prev = R(1e30);   // size of the previous Newton step
+    for (int it = 0; it < kMaxIt; ++it) {
+        const R om = R(1) - K.beta * gam;
+        R x[9];
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            x[i] = (om * dh[i] - tbm1 * ds[i]) * wr[i];
+            ok = ok && (x[i] > R(-1));
+        }
+        if (!ok) break;
+        R F = R(0), D = R(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            F = fmaR(dh[i], log1p(x[i]), F);
+            D = fmaR(-K.beta * dh[i] * dh[i] * wr[i], rcpR(R(1) + x[i]), D);
+        }
+        if (!(D < R(0))) break;
+        const R step = divR(F, D);
+        gam -= step;
+        const R as = fabs(step);
+        if (as <= tol * fabs(gam) || as > R(0.5) * prev) break;
+        prev = as;
+    }
+    return gam;
+}
+
 // One collision on the deviations g (in place).  Returns the gamma used.
 template <typename R, int COLL, int VAR, int GM>
 __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
@@ -209,16 +258,21 @@ __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
             d[8] = fmaR(R(1.0 / 12.0), umv, dm);
             d[6] = fmaR(R(-1.0 / 12.0), umv, dm);
             R a = R(0), b = R(0), c = R(0);
+            R w[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const R w = rcpR(d[i]);
-                const R wh = dh[i] * w;
+                w[i] = rcpR(d[i]);
+                const R wh = dh[i] * w[i];
                 a = fmaR(ds[i], wh, a);
                 b = fmaR(dh[i], wh, b);
-                c = fmaR(ds[i] * w, ds[i], c);
+                c = fmaR(ds[i] * w[i], ds[i], c);
             }
             const R gs = fmaR(-K.two_m_inv_beta, divR(a, b), K.inv_beta);
-            gam = (b <= K.guard * c) ? R(2) : gs;
+            const bool guarded = (b <= K.guard * c);
+            gam = guarded ? R(2) : gs;
+            if constexpr (GM == GEXACT) {
+                if (!guarded) gam = exact_gamma<R>(gs, ds, dh, w, ir, K);
+            }
         }
         // f' = f - beta (2 ds + gamma dh), eqs. (Egeneral), (ksh-mirror)
         const R tb = R(2) * K.beta, bg = K.beta * gam;

@@ -97,6 +97,13 @@ struct EnsOp {
     }
     static int run(const Lattice& L, const EnsLaunch& a) {
         (void)L;
+        if constexpr (GM == GEXACT) {
+            return -5;   // ensembles use the estimate or a fixed stabiliser
+        } else {
+            return shapes(a);
+        }
+    }
+    static int shapes(const EnsLaunch& a) {
         const StepShape& sh = a.shape;
         const int key = sh.width * 16 + sh.rpt;
         if (sh.nt) {

@@ -108,6 +108,7 @@ int dispatch_gm(int gm, A&&... a) {
     switch (gm) {
         case GEST: return Op<F, KBCC, V, GEST>::run(a...);
         case GFIX: return Op<F, KBCC, V, GFIX>::run(a...);
+        case GEXACT: return Op<F, KBCC, V, GEXACT>::run(a...);
         default: return -5;
     }
 }

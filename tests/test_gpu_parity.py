@@ -319,3 +319,80 @@ def test_zero_steps_and_copy_probe():
     a = s.get_populations()
     s.step(0)
     assert torch.equal(a, s.get_populations()) and s.steps == 0
+
+
+# ------------------------------------------------------- exact stabiliser
+@pytest.mark.parametrize("var", ["A", "B", "C", "D"])
+def test_exact_gamma_parity(orc, var):
+    """The exact stabiliser: the root of eq. (result1) by Newton's method from
+    gamma*, per node, against the oracle's Newton (which takes ln(1 + x)
+    where the kernel takes log1p(x); both stop at a relative step of 1e-15
+    in FP64, the kernel also once its steps stop shrinking, i.e. at rounding
+    noise).  FP64: gamma field to 1e-10 relative to max(1, |gamma|)
+    per node (variant C reaches gamma ~ 7) and the state after 1 and 10
+    steps to 1e-12.  FP32 (tolerance 5e-7 per Newton
+    step): populations after one step to 2e-5, as for gamma*.  The exact root
+    must differ from gamma* (the iteration did something) on this
+    non-equilibrium state."""
+    nx, ny = 67, 45
+    say("exact gamma", var)
+    beta = beta_from_nu(1e-4)
+    f0 = random_state(orc, nx, ny, beta, seed=60, eps=5e-3)
+    p = orc_params(orc, nx, ny, beta, "kbc", var, gamma_mode=orc.GAMMA_EXACT)
+    pe = orc_params(orc, nx, ny, beta, "kbc", var)
+    ogam = orc.gamma_field(p, f0)
+    ogam_est = orc.gamma_field(pe, f0)
+    assert np.abs(ogam - ogam_est).max() > 1e-6
+    z = np.zeros((ny, nx))
+    s = Sim(nx, ny, beta, collision="kbc", variant=var, form="f64", gamma_mode="exact")
+    s.init(z, z, mode="eq")
+    s.set_populations(f0)
+    gam = s.moments(gamma=True)[3].cpu().numpy()
+    say("  gamma diff", np.abs(gam - ogam).max(), "exact - estimate", np.abs(ogam - ogam_est).max())
+    assert (np.abs(gam - ogam) <= 1e-10 * np.maximum(1.0, np.abs(ogam))).all()
+    for steps in (1, 10):
+        s.set_populations(f0)
+        s.step(steps)
+        err = pop_err(s.get_populations().cpu().numpy(), orc.run(p, f0, steps))
+        say("  f64 steps", steps, "err", err)
+        assert err < 1e-12
+    s32 = Sim(nx, ny, beta, collision="kbc", variant=var, form="f32", gamma_mode="exact")
+    s32.init(z, z, mode="eq")
+    s32.set_populations(f0)
+    f0r = s32.get_populations().cpu().numpy()
+    s32.step(1)
+    err = pop_err(s32.get_populations().cpu().numpy(), orc.run(p, f0r, 1))
+    say("  f32 one step err", err)
+    assert err < 2e-5
+
+
+@pytest.mark.parametrize("form", ["f32", "f64"])
+def test_exact_gamma_fused_and_tiles_bitwise(form):
+    """The exact stabiliser runs in the single-step kernel (any tile) and in
+    the fused two-step kernel with identical bits."""
+    nx, ny = 131, 37
+    ux, uy = inputs.spectral(256, 4, 0.05, seed=22)
+    ux, uy = np.ascontiguousarray(ux[:ny, :nx]), np.ascontiguousarray(uy[:ny, :nx])
+    outs = []
+    for fusion, tile in (((1, 0), (64, 4, False)), ((1, 0), (256, 1, True)), ((2, 16), None), ((2, 8), None)):
+        s = Sim(nx, ny, beta_from_nu(1e-4), variant="B", form=form, gamma_mode="exact", fusion=fusion, tile=tile)
+        s.init(ux, uy)
+        s.step(6)
+        outs.append(s.planes(s.state_buffer()).clone())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_exact_gamma_unsupported_paths():
+    """The adjoint and the ensemble refuse the exact stabiliser cleanly."""
+    from paper_1507_02509_amd import _lib as L
+    from paper_1507_02509_amd.ensemble import Ensemble
+    nx = ny = 32
+    s = Sim(nx, ny, beta_from_nu(1e-3), variant="B", form="f32", gamma_mode="exact")
+    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)))
+    lam_a, lam_b = s.new_adjoint().zero_(), s.new_adjoint()
+    with pytest.raises(L.KbcError):
+        s.adjoint_step(s.state_buffer(), lam_a, lam_b)
+    torch.cuda.synchronize()
+    with pytest.raises(L.KbcError):
+        Ensemble([s])
