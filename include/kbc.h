@@ -263,8 +263,19 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count);
  * 256 x 1 or 256 x 2; flags as for lbm_set_tile.  Synchronises the stream. */
 int lbm_ensemble_set_tile(lbm_ens* e, int32_t width, int32_t rows_per_thread, int32_t flags);
 
-/* Advance every member nsteps: persistent = 0 launches once per step over all
- * members' tiles.  persistent = 1 (one cooperative launch of resident
+/* Steps per launch of lbm_ensemble_step: 1, or 2 (the fused two-step tile of
+ * lbm_set_fusion for every member, 64 x `rows` tiles, rows in {8, 16}; 0
+ * keeps the current height).  Defaults: 2 steps with 16 rows for FP32, 8
+ * rows for FP64, 1 step for FP16.  Bitwise identical either way; the
+ * non-temporal flag of lbm_ensemble_set_tile applies to both.
+ * lbm_ensemble_get_fusion returns the steps per launch and stores the rows in
+ * *rows when not NULL (-1 for a NULL ensemble).  set_fusion with new rows
+ * synchronises the stream. */
+int lbm_ensemble_set_fusion(lbm_ens* e, int32_t steps_per_launch, int32_t rows);
+int lbm_ensemble_get_fusion(const lbm_ens* e, int32_t* rows);
+
+/* Advance every member nsteps: persistent = 0 launches once per step (or per
+ * pair of steps, see lbm_ensemble_set_fusion) over all members' tiles.  persistent = 1 (one cooperative launch of resident
  * workgroups looping over the steps with a grid-wide barrier in between) is
  * built but switched off and returns LBM_EUNSUPPORTED: its first run on the
  * GPU did not finish and the cause has not been shown.  All members must hold

@@ -72,6 +72,8 @@ _SIGS = {
     "lbm_ensemble_create": (_c.c_int, [_c.POINTER(_vp), _c.POINTER(_vp), _c.c_int32]),
     "lbm_ensemble_set_tile": (_c.c_int, [_vp, _c.c_int32, _c.c_int32, _c.c_int32]),
     "lbm_ensemble_step": (_c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    "lbm_ensemble_set_fusion": (_c.c_int, [_vp, _c.c_int32, _c.c_int32]),
+    "lbm_ensemble_get_fusion": (_c.c_int, [_vp, _c.POINTER(_c.c_int32)]),
     "lbm_ensemble_blocks": (_c.c_int, [_vp]),
     "lbm_ensemble_free": (_c.c_int, [_vp]),
     "lbm_set_adjoint_gamma": (_c.c_int, [_vp, _c.c_int32]),

@@ -25,6 +25,8 @@ from . import _lib
 STEP_TILES = [(w, r, nt) for (w, r) in ((64, 1), (64, 4), (128, 1), (128, 2), (128, 4), (256, 1), (256, 2))
               for nt in (False, True)]
 ENSEMBLE_TILES = [(w, r, nt) for (w, r) in ((128, 2), (256, 1), (256, 2)) for nt in (False, True)]
+ENSEMBLE_CANDIDATES = ([("single",) + t for t in ENSEMBLE_TILES] +
+                       [("fused", rows, nt) for rows in (8, 16) for nt in (False, True)])
 # launch configurations of a single lattice: ("single", width, rows per
 # thread, nt) or ("fused", tile rows, nt) (two steps per launch)
 STEP_CANDIDATES = ([("single",) + t for t in STEP_TILES] +
@@ -78,7 +80,7 @@ def _time(run, steps: int, reps: int) -> float:
 
 
 def _sim_key(sim) -> str:
-    return "|".join(["sim", torch.cuda.get_device_name(sim.device), str(sim.form), str(sim.params.collision),
+    return "|".join(["sim2", torch.cuda.get_device_name(sim.device), str(sim.form), str(sim.params.collision),
                      str(sim.params.variant), f"{sim.nx}x{sim.ny}"])
 
 
@@ -115,33 +117,44 @@ def tune_sim(sim, steps: int = 10, reps: int = 3, candidates=None, use_cache: bo
     return best, timings
 
 
+def apply_ensemble_config(ens, cand):
+    """Set a launch configuration from ENSEMBLE_CANDIDATES on an Ensemble."""
+    if cand[0] == "single":
+        ens.set_fusion(1)
+        ens.set_tile(*cand[1:])
+    else:
+        ens.set_tile(256, 1, cand[2])
+        ens.set_fusion(2, cand[1])
+
+
 def _ens_key(ens) -> str:
     m0 = ens.members[0]
     sizes = hashlib.sha1(",".join(f"{m.nx}x{m.ny}" for m in ens.members).encode()).hexdigest()[:12]
-    return "|".join(["ensemble", torch.cuda.get_device_name(m0.device), str(m0.form), str(m0.params.collision),
+    return "|".join(["ensemble2", torch.cuda.get_device_name(m0.device), str(m0.form), str(m0.params.collision),
                      str(m0.params.variant), str(len(ens.members)), sizes])
 
 
 def tune_ensemble(ens, steps: int = 10, reps: int = 3, persistent: bool = False, candidates=None,
                   use_cache: bool = True):
-    """Choose and apply the fastest ensemble tile; returns the tile and timings."""
+    """Choose and apply the fastest ensemble launch configuration; returns the
+    chosen entry of ENSEMBLE_CANDIDATES and the timings."""
     path = cache_path()
     key = _ens_key(ens) + f"|{'persistent' if persistent else 'per-step'}"
     cache = _load(path) if use_cache else {}
     if use_cache and key in cache:
         best = tuple(cache[key]["tile"])
-        ens.set_tile(*best)
+        apply_ensemble_config(ens, best)
         return best, cache[key].get("ms", {})
     steps += steps % 2
     snaps = [m.state_buffer().clone() for m in ens.members]
     n0 = [m.steps for m in ens.members]
     timings = {}
-    for cand in candidates or ENSEMBLE_TILES:
-        ens.set_tile(*cand)
+    for cand in candidates or ENSEMBLE_CANDIDATES:
+        apply_ensemble_config(ens, cand)
         ens.step(2, persistent)
         timings[cand] = _time(lambda k: ens.step(k, persistent), steps, reps)
     best = min(timings, key=timings.get)
-    ens.set_tile(*best)
+    apply_ensemble_config(ens, best)
     for m, snap, n in zip(ens.members, snaps, n0):
         m.state_buffer().copy_(snap)
         m.lib.lbm_set_step(m.ctx, n)

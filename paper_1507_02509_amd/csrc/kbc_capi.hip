@@ -442,9 +442,13 @@ struct lbm_ens {
     std::vector<lbm_ctx*> m;
     kbc::Lattice L;             // common form, collision, variant, stabiliser, stream
     kbc::StepShape shape;
-    kbc::EnsEntry* dtab;
+    kbc::EnsEntry* dtab;        // member table for single-step tiles
     int ntiles;
     int blocks;                 // resident workgroups for the persistent launch
+    int fuse;                   // steps per launch: 1 or 2
+    int rows;                   // fused tile height: 8 or 16
+    kbc::EnsEntry* dtab2;       // member table for fused 64 x rows tiles
+    int ntiles2;
 };
 
 namespace {
@@ -454,10 +458,10 @@ bool ens_shape_ok(const kbc::StepShape& s) {
            (s.nt == 0 || s.nt == 1);
 }
 
-int ens_build(lbm_ens* e) {
-    std::vector<kbc::EnsEntry> tab(e->m.size());
+// Member table for tiles tw x th; returns the number of tiles or -1.
+int64_t ens_table(const lbm_ens* e, int tw, int th, std::vector<kbc::EnsEntry>& tab) {
+    tab.assign(e->m.size(), kbc::EnsEntry{});
     int64_t tiles = 0;
-    const int tw = e->shape.width, th = (256 / e->shape.width) * e->shape.rpt;
     for (size_t r = 0; r < e->m.size(); ++r) {
         const lbm_ctx* c = e->m[r];
         kbc::EnsEntry& t = tab[r];
@@ -469,7 +473,7 @@ int ens_build(lbm_ens* e) {
         t.pitch = c->L.pitch;
         t.tile_start = static_cast<int32_t>(tiles);
         tiles += static_cast<int64_t>(t.ntx) * ((c->p.ny + th - 1) / th);
-        if (tiles > (int64_t{1} << 30)) return fail(LBM_EINVAL, "ensemble has too many tiles");
+        if (tiles > (int64_t{1} << 30)) return -1;
         t.beta = c->L.beta;
         t.inv_beta = 1.0 / c->L.beta;
         t.two_m_inv_beta = 2.0 - 1.0 / c->L.beta;
@@ -477,17 +481,35 @@ int ens_build(lbm_ens* e) {
         t.guard = c->L.guard;
         t.gamma_fixed = c->L.gamma_fixed;
     }
-    if (!e->dtab) {
-        hipError_t err = hipMalloc(&e->dtab, tab.size() * sizeof(kbc::EnsEntry));
+    return tiles;
+}
+
+int ens_upload(lbm_ens* e, kbc::EnsEntry** dst, const std::vector<kbc::EnsEntry>& tab) {
+    if (!*dst) {
+        hipError_t err = hipMalloc(dst, tab.size() * sizeof(kbc::EnsEntry));
         if (err != hipSuccess) {
-            e->dtab = nullptr;
+            *dst = nullptr;
             return fail(LBM_ENOMEM, "ensemble table: %s", hipGetErrorString(err));
         }
     }
     hipError_t err = hipStreamSynchronize(e->L.stream);
     if (err == hipSuccess)
-        err = hipMemcpy(e->dtab, tab.data(), tab.size() * sizeof(kbc::EnsEntry), hipMemcpyHostToDevice);
+        err = hipMemcpy(*dst, tab.data(), tab.size() * sizeof(kbc::EnsEntry), hipMemcpyHostToDevice);
     if (err != hipSuccess) return hip_fail(err, "ensemble table upload");
+    return LBM_OK;
+}
+
+int ens_build(lbm_ens* e) {
+    std::vector<kbc::EnsEntry> tab;
+    const int64_t tiles = ens_table(e, e->shape.width, (256 / e->shape.width) * e->shape.rpt, tab);
+    const int64_t tiles2 = tiles < 0 ? -1 : ens_table(e, 64, e->rows, tab);
+    if (tiles < 0 || tiles2 < 0) return fail(LBM_EINVAL, "ensemble has too many tiles");
+    int rc = ens_upload(e, &e->dtab2, tab);
+    if (rc) return rc;
+    e->ntiles2 = static_cast<int>(tiles2);
+    ens_table(e, e->shape.width, (256 / e->shape.width) * e->shape.rpt, tab);
+    rc = ens_upload(e, &e->dtab, tab);
+    if (rc) return rc;
     e->ntiles = static_cast<int>(tiles);
     kbc::EnsLaunch a{};
     a.shape = e->shape;
@@ -523,10 +545,15 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
         e->shape.rpt = 2;
     }
     e->dtab = nullptr;
+    e->dtab2 = nullptr;
     e->blocks = 0;
+    // two fused steps per launch where the single lattice uses them
+    e->fuse = (m0->p.form == LBM_F16DEV_F32) ? 1 : 2;
+    e->rows = (m0->p.form == LBM_F64) ? 8 : 16;
     int rc = ens_build(e);
     if (rc) {
         if (e->dtab) (void)hipFree(e->dtab);
+        if (e->dtab2) (void)hipFree(e->dtab2);
         delete e;
         return rc;
     }
@@ -559,32 +586,68 @@ int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent) {
     const int cur = e->m[0]->cur;
     for (size_t r = 1; r < e->m.size(); ++r)
         if (e->m[r]->cur != cur) return fail(LBM_EINVAL, "members hold their states in different buffers");
+    const int pairs = (e->fuse == 2) ? nsteps / 2 : 0;
+    const int singles = nsteps - 2 * pairs;
     kbc::EnsLaunch a{};
-    a.table = e->dtab;
     a.nmem = static_cast<int>(e->m.size());
-    a.ntiles = e->ntiles;
-    a.nsteps = nsteps;
-    a.parity = cur;
-    a.persistent = persistent != 0;
+    a.persistent = false;
     a.blocks = e->blocks;
     a.shape = e->shape;
     a.stream = e->L.stream;
-    const int rc = kbc::launch_ensemble(e->L, a);
-    if (rc) return launch_result(rc, "lbm_ensemble_step");
+    a.rows = e->rows;
+    int par = cur;
+    if (pairs) {
+        a.table = e->dtab2;
+        a.ntiles = e->ntiles2;
+        a.nsteps = pairs;
+        a.parity = par;
+        const int rc = kbc::launch_ensemble2(e->L, a);
+        if (rc) return launch_result(rc, "lbm_ensemble_step (two fused steps)");
+        par ^= (pairs & 1);
+    }
+    if (singles) {
+        a.table = e->dtab;
+        a.ntiles = e->ntiles;
+        a.nsteps = singles;
+        a.parity = par;
+        const int rc = kbc::launch_ensemble(e->L, a);
+        if (rc) return launch_result(rc, "lbm_ensemble_step");
+        par ^= (singles & 1);
+    }
     for (lbm_ctx* c : e->m) {
-        c->cur ^= (nsteps & 1);
+        c->cur = par;
         c->steps += nsteps;
     }
     return LBM_OK;
 }
 
+int lbm_ensemble_set_fusion(lbm_ens* e, int32_t steps_per_launch, int32_t rows) {
+    if (!e) return fail(LBM_EINVAL, "ensemble is NULL");
+    if (steps_per_launch != 1 && steps_per_launch != 2)
+        return fail(LBM_EINVAL, "steps_per_launch must be 1 or 2 (got %d)", steps_per_launch);
+    if (rows != 0 && rows != 8 && rows != 16) return fail(LBM_EINVAL, "rows must be 0 (keep), 8 or 16 (got %d)", rows);
+    e->fuse = steps_per_launch;
+    if (rows && rows != e->rows) {
+        e->rows = rows;
+        return ens_build(e);
+    }
+    return LBM_OK;
+}
+
+int lbm_ensemble_get_fusion(const lbm_ens* e, int32_t* rows) {
+    if (!e) return -1;
+    if (rows) *rows = e->rows;
+    return e->fuse;
+}
+
 int lbm_ensemble_free(lbm_ens* e) {
     if (!e) return LBM_OK;
     int rc = LBM_OK;
-    if (e->dtab) {
+    if (e->dtab || e->dtab2) {
         hipError_t err = hipStreamSynchronize(e->L.stream);
         if (err != hipSuccess) rc = hip_fail(err, "lbm_ensemble_free sync");
-        (void)hipFree(e->dtab);
+        if (e->dtab) (void)hipFree(e->dtab);
+        if (e->dtab2) (void)hipFree(e->dtab2);
     }
     delete e;
     return rc;

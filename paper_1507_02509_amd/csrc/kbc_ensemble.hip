@@ -16,10 +16,15 @@
 //     fences make the new states of every XCD visible to all others).
 // Both modes run the per-node code of the single-lattice step on the same
 // tiles, so results are bitwise identical to stepping each member alone.
+//
+// k_ens2 advances every member by two fused steps per launch (the tile body
+// of the single-lattice fused kernel, 64 x TH output tiles, one workgroup per
+// tile), again bitwise identical to single steps.
 #include <hip/hip_cooperative_groups.h>
 
 #include "kbc_launch.hpp"
 #include "kbc_tile.hpp"
+#include "kbc_tile2.hpp"
 
 namespace kbc {
 
@@ -61,6 +66,63 @@ __global__ __launch_bounds__(256) void k_ens(const EnsEntry* __restrict__ tab, i
         if (s + 1 < nsteps) cooperative_groups::this_grid().sync();
     }
 }
+
+template <int FORM, int COLL, int VAR, int GM, int TH, bool NT>
+__global__ __launch_bounds__(256) void k_ens2(const EnsEntry* __restrict__ tab, int nmem, int ntiles,
+                                              int per_xcd, int parity) {
+    using F = Form<FORM>;
+    using S = typename F::S;
+    using R = typename F::R;
+    const int b = blockIdx.x;
+    const int t = (b & 7) * per_xcd + (b >> 3);
+    if (t >= ntiles) return;   // the whole workgroup leaves together
+    int lo = 0, hi = nmem - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].tile_start <= t) lo = mid; else hi = mid - 1;
+    }
+    const EnsEntry& e = tab[lo];
+    Coef<R> K;
+    K.beta = static_cast<R>(e.beta);
+    K.inv_beta = static_cast<R>(e.inv_beta);
+    K.two_m_inv_beta = static_cast<R>(e.two_m_inv_beta);
+    K.rho0 = static_cast<R>(e.rho0);
+    K.guard = static_cast<R>(e.guard);
+    K.gamma_fixed = static_cast<R>(e.gamma_fixed);
+    const int lt = t - e.tile_start;
+    step2_tile<FORM, COLL, VAR, GM, TH, NT>(static_cast<const S*>(e.buf[parity]), static_cast<S*>(e.buf[parity ^ 1]),
+                                            e.nx, e.ny, e.pitch, (lt % e.ntx) * 64, (lt / e.ntx) * TH, K);
+}
+
+// one fused launch per two steps: a.nsteps launches, each src -> dst
+template <int FORM, int COLL, int VAR, int GM>
+struct Ens2Op {
+    template <int TH, bool NT>
+    static int go(const EnsLaunch& a) {
+        const int per_xcd = (a.ntiles + 7) / 8;
+        for (int s = 0; s < a.nsteps; ++s) {
+            const int par = (a.parity + s) & 1;
+            k_ens2<FORM, COLL, VAR, GM, TH, NT><<<dim3(8u * static_cast<unsigned>(per_xcd)), dim3(256), 0, a.stream>>>(
+                a.table, a.nmem, a.ntiles, per_xcd, par);
+            if (hipGetLastError() != hipSuccess) return -2;
+        }
+        return 0;
+    }
+    static int run(const Lattice& L, const EnsLaunch& a) {
+        (void)L;
+        if constexpr (GM == GEXACT) {
+            return -5;
+        } else {
+            switch (a.rows * 2 + (a.shape.nt ? 1 : 0)) {
+                case 8 * 2: return go<8, false>(a);
+                case 8 * 2 + 1: return go<8, true>(a);
+                case 16 * 2: return go<16, false>(a);
+                case 16 * 2 + 1: return go<16, true>(a);
+                default: return -1;
+            }
+        }
+    }
+};
 
 template <int FORM, int COLL, int VAR, int GM>
 struct EnsOp {
@@ -126,5 +188,6 @@ struct EnsOp {
 }  // namespace
 
 int launch_ensemble(const Lattice& L, const EnsLaunch& a) { return dispatch<EnsOp>(L, a); }
+int launch_ensemble2(const Lattice& L, const EnsLaunch& a) { return dispatch<Ens2Op>(L, a); }
 
 }  // namespace kbc

@@ -64,8 +64,12 @@ struct EnsLaunch {
     StepShape shape;        // (128,2), (256,1) or (256,2), with or without nt
     hipStream_t stream;
     int* query_blocks;      // if set: only report the resident-workgroup count
+    int rows;               // fused launches: output tile height (8 or 16)
 };
 int launch_ensemble(const Lattice& L, const EnsLaunch& a);
+// two fused steps per launch for every member; a.nsteps counts launches, the
+// table's tiles are 64 x a.rows (kbc_ensemble.hip)
+int launch_ensemble2(const Lattice& L, const EnsLaunch& a);
 
 // adjoint (kbc_adjoint.hip).  An adjoint step writes its per-workgroup
 // dL/dbeta sums as one slice of adjoint_slice_len(L) doubles to `slice`

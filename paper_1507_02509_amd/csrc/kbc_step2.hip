@@ -1,144 +1,26 @@
-// kbc_step2.hip -- two fused time steps per launch (temporal blocking).
+// kbc_step2.hip -- two fused time steps per launch (temporal blocking) on a
+// single lattice; the tile body is step2_tile (kbc_tile2.hpp).
 //
-// A workgroup owns an output tile of 64 x TH nodes (TH = 8, 16, 24 or 32;
-// the larger ones only where the LDS tile fits a CU).
-// Step 1 runs on the tile extended by one node on every side (66 x (TH + 2)
-// nodes, periodic): each
-// node gathers its populations from the state buffer exactly as the single
-// step does (f_i at x - v_i), collides, and keeps the post-collision values
-// in LDS in the storage form.  Step 2 then gathers, for every output node,
-// population i from the LDS copy at x - v_i, collides and writes the result
-// to the destination buffer.  HBM traffic is the single step's 18 values per
-// node for two steps; the ring of extra step-1 collisions costs
-// (66 (TH + 2)) / (64 TH) - 1 more arithmetic (16 % for TH = 16, 8 % for
-// TH = 32).  The
-// values that pass through LDS are rounded to the storage form exactly as the
-// single step rounds them on the way to HBM, and both steps run the same
-// collision code, so two fused steps are bitwise identical to two single
-// steps.
-//
-// Work split: the 64 interior columns of every extended row are one wave
-// (lane = column), so the row is uniform across the wave and its bases are
-// scalar, as in the single step; the rows go to the four waves round-robin.
-// The two halo columns (2 (TH + 2) nodes) go to the lanes of wave 3 (one
-// pass, two for TH = 32), with per-lane addressing.  Grid: 1-D, tiles renumbered so that each XCD
-// sweeps one contiguous band (workgroup b runs on XCD b % 8), so the tiles
-// whose extended regions overlap run close together and their shared loads
-// hit in L2.
+// Grid: 1-D, one workgroup per 64 x TH output tile, renumbered so that each
+// XCD sweeps one contiguous band of tiles in row-major order (workgroup b runs
+// on XCD b % 8): tiles whose extended regions overlap in x run close together
+// and their shared loads hit in L2.
 #include "kbc_launch.hpp"
-#include "kbc_tile.hpp"
+#include "kbc_tile2.hpp"
 
 namespace kbc {
 
 namespace {
-
-__device__ __forceinline__ int pmod(int v, int n) {
-    const int r = v % n;
-    return r < 0 ? r + n : r;
-}
-
-// v mod n for a wave-uniform v within a few periods of [0, n): scalar loops
-// instead of an integer division
-__device__ __forceinline__ int wrap_uniform(int v, int n) {
-    while (v < 0) v += n;
-    while (v >= n) v -= n;
-    return v;
-}
-
-// v mod n for v in [-1, n]
-__device__ __forceinline__ int wrap1(int v, int n) {
-    v = (v < 0) ? v + n : v;
-    return (v >= n) ? v - n : v;
-}
 
 template <int FORM, int COLL, int VAR, int GM, int TH, bool NT>
 __global__ __launch_bounds__(256) void k_step2(const typename Form<FORM>::S* __restrict__ src,
                                                typename Form<FORM>::S* __restrict__ dst, int nx, int ny,
                                                int64_t pitch, int ntx, int ntiles, int per_xcd,
                                                Coef<typename Form<FORM>::R> K) {
-    using F = Form<FORM>;
-    using R = typename F::R;
-    using S = typename F::S;
-    constexpr int TW = 64, EW = TW + 2, EH = TH + 2;
-    __shared__ S mid[9][EH][EW];
-
     const int b = blockIdx.x;
     const int t = (b & 7) * per_xcd + (b >> 3);
     if (t >= ntiles) return;   // the whole workgroup leaves together
-    const int x0 = (t % ntx) * TW, y0 = (t / ntx) * TH;
-    const int lane = static_cast<int>(threadIdx.x & 63u);
-    const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));   // wave index
-
-    // ---- step 1, interior columns x0 .. x0 + 63 (wrapped), extended rows;
-    // the next row's loads are issued before the current row collides
-    {
-        const int gx = pmod(x0 + lane, nx);
-        const uint32_t c0 = static_cast<uint32_t>(gx) * sizeof(S);
-        const uint32_t cm = static_cast<uint32_t>(gx == 0 ? nx - 1 : gx - 1) * sizeof(S);
-        const uint32_t cp = static_cast<uint32_t>(gx == nx - 1 ? 0 : gx + 1) * sizeof(S);
-        auto load_row = [&](int ey, S (&v)[9]) {
-            const int y = wrap_uniform(y0 - 1 + ey, ny);
-            const int ym = (y == 0) ? ny - 1 : y - 1;
-            const int yp = (y == ny - 1) ? 0 : y + 1;
-            v[0] = ld_at(row_ptr(src, y, 0, pitch), c0);
-            v[1] = ld_at(row_ptr(src, y, 1, pitch), cm);
-            v[2] = ld_at(row_ptr(src, ym, 2, pitch), c0);
-            v[3] = ld_at(row_ptr(src, y, 3, pitch), cp);
-            v[4] = ld_at(row_ptr(src, yp, 4, pitch), c0);
-            v[5] = ld_at(row_ptr(src, ym, 5, pitch), cm);
-            v[6] = ld_at(row_ptr(src, ym, 6, pitch), cp);
-            v[7] = ld_at(row_ptr(src, yp, 7, pitch), cp);
-            v[8] = ld_at(row_ptr(src, yp, 8, pitch), cm);
-        };
-        S nxt[9];
-        load_row(w, nxt);
-        for (int ey = w; ey < EH; ey += 4) {
-            R g[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] = F::dec(nxt[i], i);
-            if (ey + 4 < EH) load_row(ey + 4, nxt);
-            collide<R, COLL, VAR, GM>(g, K);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) mid[i][ey][lane + 1] = F::enc(g[i], i);
-        }
-    }
-    // ---- step 1, halo columns x0 - 1 and x0 + 64 (wrapped), every extended
-    // row: 2 (TH + 2) nodes for the lanes of wave 3
-    if (w == 3) {
-        for (int k = lane; k < 2 * EH; k += 64) {
-            const int side = k / EH;
-            const int ey = k - side * EH;
-            const int gx = pmod(side ? x0 + TW : x0 - 1, nx);
-            const int y = pmod(y0 - 1 + ey, ny);
-            R g[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const int xs = wrap1(gx - kCx[i], nx), ys = wrap1(y - kCy[i], ny);
-                g[i] = F::dec(src[(static_cast<int64_t>(ys) * 9 + i) * pitch + xs], i);
-            }
-            collide<R, COLL, VAR, GM>(g, K);
-            const int ex = side ? EW - 1 : 0;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) mid[i][ey][ex] = F::enc(g[i], i);
-        }
-    }
-    __syncthreads();
-
-    // ---- step 2 on the output tile, populations gathered from LDS
-    const int gx = x0 + lane;
-    const uint32_t c0 = static_cast<uint32_t>(gx) * sizeof(S);
-    for (int oy = w; oy < TH; oy += 4) {
-        const int y = y0 + oy;
-        if (y >= ny) break;
-        if (gx < nx) {
-            R g[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] = F::dec(mid[i][oy + 1 - kCy[i]][lane + 1 - kCx[i]], i);
-            collide<R, COLL, VAR, GM>(g, K);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) st_at<NT>(row_ptr(dst, y, i, pitch), c0, F::enc(g[i], i));
-        }
-    }
+    step2_tile<FORM, COLL, VAR, GM, TH, NT>(src, dst, nx, ny, pitch, (t % ntx) * 64, (t / ntx) * TH, K);
 }
 
 template <int FORM, int COLL, int VAR, int GM>

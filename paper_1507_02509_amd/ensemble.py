@@ -34,6 +34,15 @@ class Ensemble:
         L.check(self.lib.lbm_ensemble_set_tile(self.h, int(width), int(rows_per_thread), 1 if nontemporal else 0),
                 "lbm_ensemble_set_tile")
 
+    def set_fusion(self, steps_per_launch: int, rows: int = 0):
+        """Steps per launch (1, or 2 = two fused steps) and the fused tile
+        height (8 or 16 rows; 0 keeps the current one)."""
+        L.check(self.lib.lbm_ensemble_set_fusion(self.h, int(steps_per_launch), int(rows)), "lbm_ensemble_set_fusion")
+
+    @property
+    def fusion(self) -> int:
+        return int(self.lib.lbm_ensemble_get_fusion(self.h, None))
+
     def step(self, n: int = 1, persistent: bool = False) -> "Ensemble":
         L.check(self.lib.lbm_ensemble_step(self.h, int(n), 1 if persistent else 0), "lbm_ensemble_step")
         return self

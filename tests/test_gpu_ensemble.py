@@ -1,5 +1,6 @@
-"""GPU tests of the ensemble kernel (uneven lattices in one launch, one
-persistent cooperative launch for many steps) and of the tile autotuner.
+"""GPU tests of the ensemble kernels (uneven lattices in one launch, single
+or two fused steps per launch; the persistent cooperative launch is switched
+off) and of the tile autotuner.
 The per-node code is shared with the single-lattice step, so an ensemble step
 must equal stepping every member alone, bit for bit."""
 import sys
@@ -59,17 +60,21 @@ def test_ensemble_equals_individual_steps(form, coll, var):
     for s in ref:
         s.step(9)
     want = states(ref)
-    for persistent in (False,):
-        for tile in ((128, 2, False), (256, 1, True), (256, 2, False)):
-            sims = build(small_specs(), form, coll, var)
-            ens = Ensemble(sims)
-            ens.set_tile(*tile)
-            ens.step(4, persistent).step(5, persistent)
-            got = states(sims)
-            for a, b in zip(got, want):
-                assert torch.equal(a, b), (persistent, tile)
-            assert all(s.steps == 9 for s in sims)
-            ens.free()
+    persistent = False
+    configs = [(tile, (1, 0)) for tile in ((128, 2, False), (256, 1, True), (256, 2, False))]
+    configs += [((256, 1, nt), fusion) for nt in (False, True) for fusion in ((2, 8), (2, 16))]
+    for tile, fusion in configs:
+        sims = build(small_specs(), form, coll, var)
+        ens = Ensemble(sims)
+        ens.set_tile(*tile)
+        ens.set_fusion(*fusion)
+        assert ens.fusion == fusion[0]
+        ens.step(4, persistent).step(5, persistent)   # pairs, then pairs and one single step
+        got = states(sims)
+        for a, b in zip(got, want):
+            assert torch.equal(a, b), (tile, fusion)
+        assert all(s.steps == 9 for s in sims)
+        ens.free()
 
 
 def test_ensemble_members_match_oracle(orc):
@@ -145,7 +150,7 @@ def test_autotuner_restores_state_and_caches(tmp_path, monkeypatch):
     sims = build(small_specs(), "f32")
     ens = Ensemble(sims)
     b2, t2 = autotune.tune_ensemble(ens, steps=2, reps=1)
-    assert b2 in autotune.ENSEMBLE_TILES
+    assert b2 in autotune.ENSEMBLE_CANDIDATES
     ref = build(small_specs(), "f32")
     for a, b in zip(states(sims), states(ref)):
         assert torch.equal(a, b)
