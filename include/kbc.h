@@ -154,6 +154,20 @@ int lbm_diagnostics(lbm_ctx* c, lbm_diag* out);
 int64_t lbm_step_count(const lbm_ctx* c);
 int lbm_set_step(lbm_ctx* c, int64_t n);
 
+/* Shell-summed spectra of f(x, t = n) on a square lattice (N x N), section
+ * "Decaying Two-Dimensional Turbulence": with u_hat the unnormalised discrete
+ * Fourier transform of each velocity component and integer wavevectors k,
+ * E_k[s] = sum over round(|k|) = s of (|ux_hat|^2 + |uy_hat|^2) / (2 N^4)
+ * (so sum_s E_k[s] = E = <|u|^2> / 2 when kmax covers every shell) and
+ * Z_k[s] = the same sum weighted by (2 pi |k| / N)^2 (enstrophy with the
+ * exact derivative, so it differs from the diagnostics' central-difference
+ * Z at high k).  E_k and Z_k are device arrays of kmax + 1 doubles (either may
+ * be NULL); shells above kmax are dropped.  Shell sums use atomic adds:
+ * repeatable to rounding, not bit for bit.  Allocates 2 N^2 + 4 N (N/2 + 1)
+ * doubles of scratch and an FFT plan on first use (kept until lbm_free).
+ * LBM_EUNSUPPORTED for non-square lattices. */
+int lbm_spectra(lbm_ctx* c, int32_t kmax, double* E_k, double* Z_k);
+
 /* Device pointer of the buffer holding the current state and of the other one. */
 void* lbm_state_buffer(const lbm_ctx* c);
 void* lbm_work_buffer(const lbm_ctx* c);

@@ -263,3 +263,29 @@ def init_adjoint(p: Params, ux, uy, lam0, rho0: float = 1.0, mode: int = INIT_GR
                                   ctypes.c_int32(mode), _ptr(lam0), _ptr(gux), _ptr(guy), _ptr(db)),
            "init_adjoint")
     return gux, guy, db
+
+
+# ------------------------------------------------------------ statistics
+def spectra(ux, uy, kmax: int):
+    """Shell-summed kinetic-energy and enstrophy spectra of a velocity field on
+    an N x N periodic lattice (turbulence statistics of section "Decaying
+    Two-Dimensional Turbulence"), written out from the definition over the
+    full plane of integer wavevectors k (|k_a| <= N/2):
+      e(k) = (|ux_hat(k)|^2 + |uy_hat(k)|^2) / (2 N^4),
+      E[s] = sum of e(k) over round(|k|) = s,
+      Z[s] = sum of e(k) (2 pi |k| / N)^2 over the same shell,
+    with u_hat the unnormalised discrete Fourier transform (numpy's fft2), so
+    that sum_s E[s] = <|u|^2> / 2 (Parseval) and sum_s Z[s] is the enstrophy
+    with the exact derivative.  Shells above kmax are dropped."""
+    ux = np.asarray(ux, dtype=np.float64)
+    uy = np.asarray(uy, dtype=np.float64)
+    n = ux.shape[0]
+    assert ux.shape == (n, n) and uy.shape == (n, n)
+    e = (np.abs(np.fft.fft2(ux)) ** 2 + np.abs(np.fft.fft2(uy)) ** 2) / (2.0 * float(n) ** 4)
+    k = np.fft.fftfreq(n, d=1.0 / n)                 # integer wavenumbers 0..n/2-1, -n/2..-1
+    k2 = k[None, :] ** 2 + k[:, None] ** 2
+    shell = np.floor(np.sqrt(k2) + 0.5).astype(np.int64)
+    keep = shell <= kmax
+    E = np.bincount(shell[keep], weights=e[keep], minlength=kmax + 1)[: kmax + 1]
+    Z = np.bincount(shell[keep], weights=(e * k2 * (2.0 * np.pi / n) ** 2)[keep], minlength=kmax + 1)[: kmax + 1]
+    return E, Z

@@ -27,6 +27,9 @@ struct lbm_ctx {
     size_t dscratch_elems;
     double* ascratch;       // adjoint: block partials + initial-state stencil fields
     size_t ascratch_elems;
+    double* sscratch;       // spectra: velocity fields and their transforms
+    size_t sscratch_elems;
+    void* fft_plan;         // spectra: cached FFT plan
 };
 
 namespace {
@@ -160,6 +163,9 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     c->dscratch_elems = 0;
     c->ascratch = nullptr;
     c->ascratch_elems = 0;
+    c->sscratch = nullptr;
+    c->sscratch_elems = 0;
+    c->fft_plan = nullptr;
     rc = kbc::launch_init(c->L, buf_a, rho, ux, uy, grad, mode);
     if (rc) {
         delete c;
@@ -317,14 +323,42 @@ int lbm_set_beta(lbm_ctx* c, double beta) {
 int lbm_free(lbm_ctx* c) {
     if (!c) return LBM_OK;
     int rc = LBM_OK;
-    if (c->dscratch || c->ascratch) {
+    if (c->dscratch || c->ascratch || c->sscratch || c->fft_plan) {
         hipError_t e = hipStreamSynchronize(c->L.stream);
         if (e != hipSuccess) rc = hip_fail(e, "lbm_free sync");
         if (c->dscratch) (void)hipFree(c->dscratch);
         if (c->ascratch) (void)hipFree(c->ascratch);
+        if (c->sscratch) (void)hipFree(c->sscratch);
+        kbc::destroy_spectra_plan(c->fft_plan);
     }
     delete c;
     return rc;
+}
+
+int lbm_spectra(lbm_ctx* c, int32_t kmax, double* E_k, double* Z_k) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->p.nx != c->p.ny) return fail(LBM_EUNSUPPORTED, "spectra need a square lattice (%d x %d)", c->p.nx, c->p.ny);
+    if (kmax < 0) return fail(LBM_EINVAL, "kmax must be >= 0");
+    if (!E_k && !Z_k) return LBM_OK;
+    const size_t n = static_cast<size_t>(c->p.nx);
+    const size_t need = 2 * n * n + 4 * n * (n / 2 + 1);
+    if (c->sscratch_elems < need) {
+        if (c->sscratch) {
+            hipError_t e = hipStreamSynchronize(c->L.stream);
+            if (e != hipSuccess) return hip_fail(e, "spectra scratch sync");
+            (void)hipFree(c->sscratch);
+            c->sscratch = nullptr;
+            c->sscratch_elems = 0;
+        }
+        hipError_t e = hipMalloc(&c->sscratch, need * sizeof(double));
+        if (e != hipSuccess) {
+            c->sscratch = nullptr;
+            return fail(LBM_ENOMEM, "spectra scratch: %s", hipGetErrorString(e));
+        }
+        c->sscratch_elems = need;
+    }
+    return launch_result(kbc::launch_spectra(c->L, c->buf[c->cur], &c->fft_plan, c->sscratch, kmax, E_k, Z_k),
+                         "lbm_spectra");
 }
 
 size_t lbm_adjoint_bytes(int32_t nx, int32_t ny, int32_t form) {

@@ -89,6 +89,13 @@ int launch_adjoint_init(const Lattice& L, const double* rho, const double* ux, c
                         const void* lam0, double* gux, double* guy, double* P, double* partials,
                         int64_t nblocks_cap, double* acc);
 
+// shell-summed energy and enstrophy spectra of a square lattice
+// (kbc_spectra.hip); *plan_slot caches the FFT plan (destroy_spectra_plan);
+// work: 2 n^2 + 4 n (n/2 + 1) doubles; ek, zk: kmax + 1 doubles (nullable)
+int launch_spectra(const Lattice& L, const void* state, void** plan_slot, double* work, int kmax, double* ek,
+                   double* zk);
+void destroy_spectra_plan(void* plan);
+
 // kernel-name lookup for profiling output
 const char* step_kernel_name(const Lattice& L);
 

@@ -145,6 +145,16 @@ class Sim:
         L.check(self.lib.lbm_set_populations(self.ctx, L.ptr(f)), "lbm_set_populations")
         self._inputs = (f,)
 
+    def spectra(self, kmax: int | None = None):
+        """Shell-summed kinetic-energy and enstrophy spectra (E_k, Z_k), FP64
+        tensors of kmax + 1 shells (default: every shell, ceil(N/sqrt 2))."""
+        if kmax is None:
+            kmax = int(np.ceil(self.nx / np.sqrt(2.0)))
+        ek = torch.empty(kmax + 1, dtype=torch.float64, device=self.device)
+        zk = torch.empty(kmax + 1, dtype=torch.float64, device=self.device)
+        L.check(self.lib.lbm_spectra(self.ctx, int(kmax), L.ptr(ek), L.ptr(zk)), "lbm_spectra")
+        return ek, zk
+
     def diagnostics(self) -> dict:
         d = L.Diag()
         L.check(self.lib.lbm_diagnostics(self.ctx, ctypes.byref(d)), "lbm_diagnostics")
