@@ -35,7 +35,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f16": 36, "f32": 72, "f64": 144}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 _CSRC = os.path.join(ROOT, "paper_1507_02509_amd", "csrc")
-STEP_SOURCES = [os.path.join(_CSRC, f) for f in ("kbc_step.hip", "kbc_step2.hip", "kbc_tile.hpp", "kbc_device.hpp")]
+STEP_SOURCES = [os.path.join(_CSRC, f)
+                for f in ("kbc_step.hip", "kbc_step2.hip", "kbc_tile.hpp", "kbc_tile2.hpp", "kbc_device.hpp")]
 # FP arithmetic operations of one KBC-B collision per node (adds, multiplies,
 # reciprocals and conversions count one, FMAs two), counted in the gfx950 code
 # of the single-step kernel; the vector peaks are MI355X's published ones
