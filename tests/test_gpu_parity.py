@@ -396,3 +396,50 @@ def test_exact_gamma_unsupported_paths():
     torch.cuda.synchronize()
     with pytest.raises(L.KbcError):
         Ensemble([s])
+
+
+# ------------------------------------------------------------ symmetries
+@pytest.mark.parametrize("form", ["f32", "f64", "f16"])
+def test_translation_invariance_bitwise(form):
+    """Shifting the initial field by (a, b) nodes shifts the state after any
+    number of steps bit for bit: every node runs the same arithmetic on the
+    same inputs, whatever tile, ring or wrap it falls in (odd step count:
+    fused pairs and one single step)."""
+    nx, ny, a, b = 131, 70, 37, 19
+    ux, uy = inputs.spectral(nx, 4, 0.05, seed=31, ny=ny)
+    out = []
+    for sx, sy in ((0, 0), (a, b)):
+        s = Sim(nx, ny, beta_from_nu(1e-4), variant="B", form=form)
+        s.init(np.roll(ux, (sy, sx), axis=(0, 1)), np.roll(uy, (sy, sx), axis=(0, 1)))
+        s.step(9)
+        out.append(s.get_populations())
+    assert torch.equal(torch.roll(out[0], (b, a), dims=(1, 2)), out[1])
+
+
+# velocity index under a quarter turn (c_x, c_y) -> (-c_y, c_x)
+ROT = [0, 2, 3, 4, 1, 6, 7, 8, 5]
+
+
+@pytest.mark.parametrize("coll,var", CASES)
+def test_quarter_turn_equivariance_f64(coll, var):
+    """Rotating the initial field by 90 degrees (positions and vectors)
+    rotates the state after 50 steps, populations relabelled by the same
+    turn, to rounding (the kernels' moment sums associate terms in an order
+    that is not symmetric under the turn, so not bit for bit)."""
+    n = 64
+    ux, uy = inputs.spectral(n, 4, 0.05, seed=32)
+    # position (x, y) -> (-y mod n, x); vector (u, v) -> (-v, u)
+    rx, ry = np.empty_like(ux), np.empty_like(uy)
+    y, x = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    rx[x, (-y) % n] = -uy[y, x]
+    ry[x, (-y) % n] = ux[y, x]
+    f0 = Sim(n, n, beta_from_nu(1e-4), collision=coll, variant=var, form="f64").init(ux, uy).step(50)
+    f1 = Sim(n, n, beta_from_nu(1e-4), collision=coll, variant=var, form="f64").init(rx, ry).step(50)
+    g0 = f0.get_populations().cpu().numpy()
+    g1 = f1.get_populations().cpu().numpy()
+    want = np.empty_like(g0)
+    for i in range(9):
+        want[ROT[i]][x, (-y) % n] = g0[i][y, x]
+    err = pop_err(g1, want)
+    say("  quarter turn", coll, var, err)
+    assert err < 1e-12
