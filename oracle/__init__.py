@@ -49,6 +49,8 @@ def lib():
         _lib.orc_node_collide.restype = ctypes.c_double
         _lib.orc_node_result1.restype = ctypes.c_double
         _lib.orc_cs2.restype = ctypes.c_double
+        _lib.orc_round_f16.restype = ctypes.c_double
+        _lib.orc_round_f16.argtypes = [ctypes.c_double]
         del dp
     return _lib
 
@@ -210,12 +212,36 @@ def step(p: Params, f, want_gamma: bool = False):
     return (out, gam) if want_gamma else out
 
 
-def run(p: Params, f, nsteps: int):
+STORE_F64, STORE_F32, STORE_F16 = 0, 1, 2
+STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "f16": STORE_F16}
+
+
+def run(p: Params, f, nsteps: int, storage: str | None = None, rho0: float = 1.0):
+    """nsteps steps from f; with storage "f32" or "f16" the state is rounded
+    to that deviation storage after every step (the caller rounds the initial
+    state with round_storage)."""
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     work = np.zeros_like(f)
     cp = p.c()
-    _check(lib().orc_run(ctypes.byref(cp), _ptr(f), _ptr(work), ctypes.c_int32(nsteps)), "run")
+    if storage is None:
+        _check(lib().orc_run(ctypes.byref(cp), _ptr(f), _ptr(work), ctypes.c_int32(nsteps)), "run")
+    else:
+        _check(lib().orc_run_stored(ctypes.byref(cp), ctypes.c_double(rho0), ctypes.c_int32(STORAGE[storage]),
+                                    _ptr(f), _ptr(work), ctypes.c_int32(nsteps)), "run_stored")
     return f
+
+
+def round_storage(p: Params, f, storage: str, rho0: float = 1.0):
+    """A copy of state f with every deviation rounded to the given storage."""
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    cp = p.c()
+    _check(lib().orc_round_storage(ctypes.byref(cp), ctypes.c_double(rho0), ctypes.c_int32(STORAGE[storage]),
+                                   _ptr(f)), "round_storage")
+    return f
+
+
+def round_f16(x: float) -> float:
+    return lib().orc_round_f16(float(x))
 
 
 def moments(p: Params, f):

@@ -205,6 +205,54 @@ int orc_run(const orc_params* p, double* f, double* work, int32_t nsteps)
     return 0;
 }
 
+/* Round to the nearest binary16 value, ties to even, written from the
+ * format's definition: 11 significant bits for normal numbers, a fixed
+ * spacing of 2^-24 below the smallest normal 2^-14, and overflow to
+ * infinity from 65520 (the midpoint above the largest finite value 65504). */
+double orc_round_f16(double x)
+{
+    if (x != x || x == 0.0 || isinf(x)) return x;
+    int e;
+    (void)frexp(x, &e);                  /* |x| in [2^(e-1), 2^e) */
+    int q = e - 11;                      /* spacing of binary16 values there */
+    if (q < -24) q = -24;
+    const double r = ldexp(rint(ldexp(x, -q)), q);   /* rint: nearest, ties to even */
+    return fabs(r) > 65504.0 ? copysign(INFINITY, x) : r;
+}
+
+int orc_round_storage(const orc_params* p, double rho0, int32_t storage, double* f)
+{
+    if (check(p) || !f || storage < ORC_STORE_F64 || storage > ORC_STORE_F16) return -1;
+    if (storage == ORC_STORE_F64) return 0;
+    const long N = (long)p->nx * p->ny;
+    for (int i = 0; i < ORC_Q; ++i) {
+        const double w = orc_weight(i) * rho0;
+        const int s = (i == 0) ? 1 : (i < 5 ? 3 : 5);
+        for (long n = 0; n < N; ++n) {
+            const double g = f[i * N + n] - w;
+            const double r = (storage == ORC_STORE_F32) ? (double)(float)g
+                                                        : ldexp(orc_round_f16(ldexp(g, s)), -s);
+            f[i * N + n] = w + r;
+        }
+    }
+    return 0;
+}
+
+int orc_run_stored(const orc_params* p, double rho0, int32_t storage, double* f, double* work, int32_t nsteps)
+{
+    if (check(p) || !f || !work || nsteps < 0) return -1;
+    double *a = f, *b = work;
+    for (int s = 0; s < nsteps; ++s) {
+        if (orc_step(p, a, b, NULL)) return -1;
+        if (orc_round_storage(p, rho0, storage, b)) return -1;
+        double* t = a;
+        a = b;
+        b = t;
+    }
+    if (a != f) memcpy(f, a, sizeof(double) * ORC_Q * (size_t)p->nx * (size_t)p->ny);
+    return 0;
+}
+
 int orc_moments(const orc_params* p, const double* f, double* rho, double* ux, double* uy)
 {
     if (check(p) || !f) return -1;

@@ -82,6 +82,18 @@ int orc_init(const orc_params* p, const double* rho, double rho0, const double* 
              const double* uy, const double* grad, int32_t mode, double* f);
 int orc_step(const orc_params* p, const double* fin, double* fout, double* gamma);
 int orc_run(const orc_params* p, double* f, double* work, int32_t nsteps);
+
+/* ---- storage rounding (emulation of reduced-precision state storage) ----
+ * ORC_STORE_F32: the deviation g_i = f_i - W_i rho0 rounded to binary32;
+ * ORC_STORE_F16: g_i 2^s_i rounded to binary16 (s = 1 for the rest
+ * population, 3 for the axis ones, 5 for the diagonals) and scaled back.
+ * Rounding is to nearest, ties to even.  orc_round_storage rounds a state in
+ * place; orc_run_stored runs nsteps steps rounding the state after each (the
+ * initial state is rounded by the caller). */
+enum { ORC_STORE_F64 = 0, ORC_STORE_F32 = 1, ORC_STORE_F16 = 2 };
+double orc_round_f16(double x);
+int orc_round_storage(const orc_params* p, double rho0, int32_t storage, double* f);
+int orc_run_stored(const orc_params* p, double rho0, int32_t storage, double* f, double* work, int32_t nsteps);
 int orc_moments(const orc_params* p, const double* f, double* rho, double* ux, double* uy);
 int orc_gamma_field(const orc_params* p, const double* f, double* gamma);
 int orc_diagnostics(const orc_params* p, const double* f, double out[ORC_NDIAG]);

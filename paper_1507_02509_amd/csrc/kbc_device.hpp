@@ -55,8 +55,10 @@ template <> struct Form<F16> {
     __device__ static __forceinline__ double dec64(S v, int i) {
         return static_cast<double>(static_cast<float>(v)) / static_cast<double>(1 << f16_shift(i));
     }
+    // one rounding, double -> binary16 (not through binary32, which would
+    // round twice and can land one unit away)
     __device__ static __forceinline__ S enc64(double v, int i) {
-        return static_cast<_Float16>(static_cast<float>(v * static_cast<double>(1 << f16_shift(i))));
+        return static_cast<_Float16>(v * static_cast<double>(1 << f16_shift(i)));
     }
 };
 

@@ -83,8 +83,9 @@ def test_adjoint_step_parity_f32(orc, coll, var):
     lam_next = np.random.default_rng(43).standard_normal((9, ny, nx))
     s = Sim(nx, ny, beta, collision=coll, variant=var, form="f32")
     s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    f0r = orc.round_storage(orc.Params(nx, ny, beta), f0, "f32")
     s.set_populations(f0)
-    f0r = s.get_populations().cpu().numpy()
+    assert np.abs(s.get_populations().cpu().numpy() - f0r).max() < 1e-15
     lam_next = lam_next.astype(np.float32).astype(np.float64)
     lout = s.new_adjoint()
     acc = torch.zeros(1, dtype=torch.float64, device="cuda")

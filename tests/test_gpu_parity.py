@@ -180,9 +180,10 @@ def test_step_parity_f32(orc, coll, var):
     f0 = random_state(orc, nx, ny, beta, seed=12, eps=1e-3)
     s = Sim(nx, ny, beta, collision=coll, variant=var, form="f32")
     s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
-    s.set_populations(f0)
-    f0r = s.get_populations().cpu().numpy()       # the stored (rounded) state
     p = orc_params(orc, nx, ny, beta, coll, var)
+    f0r = orc.round_storage(p, f0, "f32")          # the stored (rounded) state
+    s.set_populations(f0)
+    assert pop_err(s.get_populations().cpu().numpy(), f0r) < 1e-12
     errs = []
     for nsteps in (1, 10):
         s2 = Sim(nx, ny, beta, collision=coll, variant=var, form="f32")
@@ -202,11 +203,12 @@ def test_step_parity_f16(orc, coll, var):
     f0 = random_state(orc, nx, ny, beta, seed=13, eps=1e-3)
     s = Sim(nx, ny, beta, collision=coll, variant=var, form="f16")
     s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    p = orc_params(orc, nx, ny, beta, coll, var)
+    f0r = orc.round_storage(p, f0, "f16")
     s.set_populations(f0)
-    f0r = s.get_populations().cpu().numpy()
+    assert pop_err(s.get_populations().cpu().numpy(), f0r) < 1e-12
     s.step(1)
-    err = pop_err(s.get_populations().cpu().numpy(),
-                  orc.run(orc_params(orc, nx, ny, beta, coll, var), f0r, 1))
+    err = pop_err(s.get_populations().cpu().numpy(), orc.run(p, f0r, 1))
     say("  f16 error", err)
     assert err < 5e-3
 
@@ -260,11 +262,13 @@ def test_diagnostics_parity(orc, form):
     say("diagnostics", form)
     beta = beta_from_nu(1e-3)
     ux, uy = inputs.spectral(nx, 3, 0.05, seed=30, ny=ny)
-    s = Sim(nx, ny, beta, form=form).init(ux, uy)
-    s.step(5)
+    p = orc_params(orc, nx, ny, beta, "kbc", "B")
+    f = orc.round_storage(p, orc.run(p, orc.init(p, ux, uy), 5), form)
+    s = Sim(nx, ny, beta, form=form)
+    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    s.set_populations(f)
     dg = s.diagnostics()
-    f = s.get_populations().cpu().numpy()
-    do = orc.diagnostics(orc_params(orc, nx, ny, beta, "kbc", "B"), f)
+    do = orc.diagnostics(p, f)
     for k in ("mass", "jx", "jy", "E", "Z", "P", "S", "n_nonfinite", "n_feq_nonpos"):
         assert dg[k] == pytest.approx(do[k], rel=1e-10, abs=1e-13), k
     for k in ("E_std", "Z_std", "P_std", "rho_std"):
@@ -358,8 +362,9 @@ def test_exact_gamma_parity(orc, var):
         assert err < 1e-12
     s32 = Sim(nx, ny, beta, collision="kbc", variant=var, form="f32", gamma_mode="exact")
     s32.init(z, z, mode="eq")
+    f0r = orc.round_storage(p, f0, "f32")
     s32.set_populations(f0)
-    f0r = s32.get_populations().cpu().numpy()
+    assert pop_err(s32.get_populations().cpu().numpy(), f0r) < 1e-12
     s32.step(1)
     err = pop_err(s32.get_populations().cpu().numpy(), orc.run(p, f0r, 1))
     say("  f32 one step err", err)
@@ -443,3 +448,42 @@ def test_quarter_turn_equivariance_f64(coll, var):
     err = pop_err(g1, want)
     say("  quarter turn", coll, var, err)
     assert err < 1e-12
+
+
+# ------------------------------------------- reduced-precision storage forms
+@pytest.mark.parametrize("form", ["f32", "f16"])
+def test_storage_forms_against_stored_oracle(orc, form):
+    """The FP32 and FP16 deviation forms against the oracle run with the same
+    storage rounding after every step (FP64 arithmetic): what remains is the
+    kernels' FP32 arithmetic.  Printed next to the error against the plain
+    FP64 oracle, which also contains the storage rounding.
+
+    The encoded initial state must equal the oracle's rounding of it (both
+    round once, to nearest even).  Bars, per-plane relative deviation error:
+    FP32 2e-6 / 1e-5 / 5e-5 after 1 / 10 / 50 steps (a few FP32 units, then
+    linear growth; measured 2.0e-7 / 3.4e-7 / 4.0e-7).  FP16: an FP32
+    difference in the collision flips a binary16 rounding now and then, one
+    binary16 unit of the scaled deviation (about 5e-4 of the plane's largest
+    deviation); such flips feed back and add up, so 1e-3 / 2e-3 / 5e-3
+    (measured 1.4e-4 / 5.9e-4 / 2.2e-3; against the unrounded FP64 oracle
+    1.1e-3 / 1.3e-3 / 2.2e-3, so the emulation accounts for the first steps'
+    error)."""
+    nx, ny = 67, 45
+    beta = beta_from_nu(1e-4)
+    f0 = random_state(orc, nx, ny, beta, seed=70)
+    p = orc_params(orc, nx, ny, beta, "kbc", "B")
+    s = Sim(nx, ny, beta, collision="kbc", variant="B", form=form)
+    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    s.set_populations(f0)
+    fs = orc.round_storage(p, f0, form)
+    assert pop_err(s.get_populations().cpu().numpy(), fs) < 1e-12
+    bars = {"f32": {1: 2e-6, 10: 1e-5, 50: 5e-5}, "f16": {1: 1e-3, 10: 2e-3, 50: 5e-3}}[form]
+    done = 0
+    for steps in (1, 10, 50):
+        s.step(steps - done)
+        done = steps
+        fg = s.get_populations().cpu().numpy()
+        e_st = pop_err(fg, orc.run(p, fs, steps, storage=form))
+        e_64 = pop_err(fg, orc.run(p, f0, steps))
+        say(f"  {form} steps {steps}: vs stored oracle {e_st:.3e}, vs FP64 oracle {e_64:.3e}")
+        assert e_st < bars[steps]
