@@ -168,75 +168,147 @@ __device__ __forceinline__ R exact_gamma(R gam, const R (&ds)[9], const R (&dh)[
 }
 
 // One collision on the deviations g (in place).  Returns the gamma used.
+//
+// Written for instruction count: the kernels that call it issue one vector
+// instruction per operation here and are bound by that issue rate, so every
+// product-plus-sum is an explicit FMA (contraction is off) and scale factors
+// are folded into the moments before they are spread back to populations.
 template <typename R, int COLL, int VAR, int GM>
 __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
+    // conserved moments, eq. (moments) restricted to the deviations
     const R s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
     const R d13 = g[1] - g[3], d24 = g[2] - g[4], d57 = g[5] - g[7], d68 = g[6] - g[8];
-    const R sd = s57 + s68;
-    const R dr = (g[0] + sd) + (s13 + s24);        // rho - rho0
-    const R jx = d13 + (d57 - d68);                // rho u_x
-    const R jy = d24 + (d57 + d68);                // rho u_y
+    const R sd = s57 + s68, sa = s13 + s24;
+    const R dr = (g[0] + sd) + sa;                 // rho - rho0
+    const R mq = d57 - d68, pq = d57 + d68;
+    const R jx = d13 + mq;                         // rho u_x
+    const R jy = d24 + pq;                         // rho u_y
     const R rho = K.rho0 + dr;
     const R ir = rcpR(rho);
     const R ux = jx * ir, uy = jy * ir;
     const R uxx = ux * ux, uyy = uy * uy, u2 = uxx + uyy;
-
     const R upv = ux + uy, umv = ux - uy;
+
     if constexpr (COLL == LBGK) {
-        // f' = f - 2 beta (f - feq), eq. (LBGKmirr) in eq. (Egeneral), with
-        // feq_i - W_i rho0 = W_i [ (rho - rho0) + rho e_i ],
+        // f' = f - 2 beta (f - feq), eq. (LBGKmirr) in eq. (Egeneral):
+        // g' = (1 - 2 beta) g + 2 beta W_i [(rho - rho0) + rho e_i],
         // e_i = 3 (v.u) + 4.5 (v.u)^2 - 1.5 |u|^2
         const R c0 = R(-1.5) * u2;
         const R bx = fmaR(R(4.5), uxx, c0), by = fmaR(R(4.5), uyy, c0);
-        const R bp = fmaR(R(4.5) * upv, upv, c0), bm = fmaR(R(4.5) * umv, umv, c0);
+        const R uxy9 = R(9) * (ux * uy);
+        const R b5 = fmaR(R(3), u2, uxy9), b6 = fmaR(R(3), u2, -uxy9);   // 4.5 (u_x +- u_y)^2 - 1.5 |u|^2
         R e[9];
         e[0] = c0;
         e[1] = fmaR(R(3), ux, bx);
         e[3] = fmaR(R(-3), ux, bx);
         e[2] = fmaR(R(3), uy, by);
         e[4] = fmaR(R(-3), uy, by);
-        e[5] = fmaR(R(3), upv, bp);
-        e[7] = fmaR(R(-3), upv, bp);
-        e[8] = fmaR(R(3), umv, bm);
-        e[6] = fmaR(R(-3), umv, bm);
-        const R tb = R(2) * K.beta;
+        e[5] = fmaR(R(3), upv, b5);
+        e[7] = fmaR(R(-3), upv, b5);
+        e[8] = fmaR(R(3), umv, b6);
+        e[6] = fmaR(R(-3), umv, b6);
+        const R tb = R(2) * K.beta, omt = R(1) - tb;
+        const R tw[3] = {tb * R(weight(0)), tb * R(weight(1)), tb * R(weight(5))};
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const R feqd = R(weight(i)) * fmaR(rho, e[i], dr);   // feq_i - W_i rho0
-            g[i] = fmaR(-tb, g[i] - feqd, g[i]);
+            const R twi = tw[i == 0 ? 0 : (i < 5 ? 1 : 2)];
+            g[i] = fmaR(omt, g[i], twi * fmaR(rho, e[i], dr));
         }
         return R(2);
     } else {
-        const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
-        const R jux = jx * ux, juy = jy * uy;
-        const R dr3 = dr * third;
-        // non-equilibrium moments of df = f - feq
-        const R dPxx = ((s13 + sd) - dr3) - jux;
-        const R dPyy = ((s24 + sd) - dr3) - juy;
-        const R dPxy = (s57 - s68) - jx * uy;
-        const R dQx = (d57 - d68) - jx * third;
-        const R dQy = (d57 + d68) - jy * third;
-        const R dA = (sd - dr * ninth) - (jux + juy) * third;
-        const R dT = dPxx + dPyy, dN = dPxx - dPyy, dP = dPxy;
+        constexpr bool kCentral = (VAR == VA || VAR == VB);   // s in the co-moving frame, eq. (cm)
+        constexpr bool kTrace = (VAR == VA || VAR == VC);     // T belongs to s
+        // non-equilibrium moments of df = f - feq (feq of second order, c_s^2 = 1/3)
+        const R juy = jy * uy;
+        const R jsum = fmaR(jx, ux, juy);          // rho |u|^2
+        const R jdif = fmaR(jx, ux, -juy);         // rho (u_x^2 - u_y^2)
+        const R dT = fmaR(R(2), sd, sa) - fmaR(R(2.0 / 3.0), dr, jsum);
+        const R dN = (s13 - s24) - jdif;
+        const R dP = fmaR(-jx, uy, s57 - s68);
+        const R dQx = fmaR(R(-1.0 / 3.0), jx, mq);
+        const R dQy = fmaR(R(-1.0 / 3.0), jy, pq);
+        const R dA = fmaR(R(-1.0 / 3.0), jsum, fmaR(R(-1.0 / 9.0), dr, sd));
+        const R uxy = ux * uy;
 
-        // shear part (s) and higher-order part (h) moments, Table kbc_moment_grouping
-        R Ts, Qxs, Qys, As;
-        if constexpr (VAR == VC) {
-            Ts = dT; Qxs = R(0); Qys = R(0); As = R(0);
-        } else if constexpr (VAR == VD) {
-            Ts = R(0); Qxs = R(0); Qys = R(0); As = R(0);
-        } else {
-            // linear part of eq. (cm) applied to the central shear moments
-            const R tT = (VAR == VA) ? dT : R(0);
-            const R hux = R(0.5) * ux, huy = R(0.5) * uy;
-            Ts = tT;
-            Qxs = fmaR(R(2) * uy, dP, hux * (tT - dN));
-            Qys = fmaR(R(2) * ux, dP, huy * (tT + dN));
-            As = fmaR(R(4) * ux * uy, dP, fmaR(R(0.5) * u2, tT, R(-0.5) * (uxx - uyy) * dN));
+        // Shear part s, Table kbc_moment_grouping: (T_s, N, Pi, Q_xyy,s, Q_yxx,s,
+        // A_s), all scaled by 1/4 (tq, nq, pq4, xq, yq, aq).  Central variants
+        // take the linear part of eq. (cm) at the node's velocity.
+        const R nq = R(0.25) * dN, pq4 = R(0.25) * dP;
+        R xq = R(0), yq = R(0), aq = R(0);
+        if constexpr (kCentral) {
+            const R p2 = R(0.5) * dP, n8 = R(0.125) * dN;
+            if constexpr (kTrace) {
+                const R t8 = R(0.125) * dT;
+                xq = fmaR(uy, p2, ux * (t8 - n8));
+                yq = fmaR(ux, p2, uy * (t8 + n8));
+                aq = fmaR(uxy, dP, fmaR(u2, t8, -((uxx - uyy) * n8)));
+            } else {
+                xq = fmaR(uy, p2, -(ux * n8));
+                yq = fmaR(ux, p2, uy * n8);
+                aq = fmaR(uxy, dP, -((uxx - uyy) * n8));
+            }
         }
-        R ds[9], dh[9];
-        moments_to_pop<R>(Ts, dN, dP, Qxs, Qys, As, ds);
-        moments_to_pop<R>(dT - Ts, R(0), R(0), dQx - Qxs, dQy - Qys, dA - As, dh);
+        // populations of s, eq. (momentsD2Q9) without mass and momentum
+        R ds[9];
+        {
+            R tpn, tmn;                              // (T_s +- N) / 4
+            if constexpr (kTrace) {
+                const R tq = R(0.25) * dT;
+                tpn = tq + nq;
+                tmn = tq - nq;
+            } else {
+                tpn = nq;
+                tmn = -nq;
+            }
+            if constexpr (kCentral) {
+                ds[0] = kTrace ? fmaR(R(4), aq, -dT) : R(4) * aq;
+                ds[1] = fmaR(R(-2), xq + aq, tpn);
+                ds[3] = fmaR(R(2), xq - aq, tpn);
+                ds[2] = fmaR(R(-2), yq + aq, tmn);
+                ds[4] = fmaR(R(2), yq - aq, tmn);
+                const R ap = aq + pq4, am = aq - pq4, xp = xq + yq, xm = xq - yq;
+                ds[5] = ap + xp;
+                ds[7] = ap - xp;
+                ds[6] = am - xm;
+                ds[8] = am + xm;
+            } else {
+                ds[0] = kTrace ? -dT : R(0);
+                ds[1] = tpn;
+                ds[3] = tpn;
+                ds[2] = tmn;
+                ds[4] = tmn;
+                ds[5] = pq4;
+                ds[7] = pq4;
+                ds[6] = -pq4;
+                ds[8] = -pq4;
+            }
+        }
+        // higher-order part h = df - s: moments (T - T_s, 0, 0, dQ - Q_s, dA - A_s) / 4
+        R dh[9];
+        {
+            const R xh = kCentral ? fmaR(R(0.25), dQx, -xq) : R(0.25) * dQx;
+            const R yh = kCentral ? fmaR(R(0.25), dQy, -yq) : R(0.25) * dQy;
+            const R ah = kCentral ? fmaR(R(0.25), dA, -aq) : R(0.25) * dA;
+            const R hp = xh + yh, hm = xh - yh;
+            dh[5] = ah + hp;
+            dh[7] = ah - hp;
+            dh[6] = ah - hm;
+            dh[8] = ah + hm;
+            if constexpr (kTrace) {
+                dh[0] = R(4) * ah;
+                dh[1] = R(-2) * (xh + ah);
+                dh[3] = R(2) * (xh - ah);
+                dh[2] = R(-2) * (yh + ah);
+                dh[4] = R(2) * (yh - ah);
+            } else {
+                const R th = R(0.25) * dT;
+                dh[0] = fmaR(R(4), ah, -dT);
+                dh[1] = fmaR(R(-2), xh + ah, th);
+                dh[3] = fmaR(R(2), xh - ah, th);
+                dh[2] = fmaR(R(-2), yh + ah, th);
+                dh[4] = fmaR(R(2), yh - ah, th);
+            }
+        }
 
         R gam;
         if constexpr (GM == GFIX) {
@@ -244,13 +316,12 @@ __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
         } else {
             // entropic scalar products, weights 1 / (W_i (1 + e_i)) = rho / feq_i;
             // d_i = W_i (1 + e_i) = W_i (1 - 1.5 |u|^2 + 4.5 (v.u)^2) + 3 W_i (v.u)
-            const R d0 = fmaR(R(-2.0 / 3.0), u2, R(4.0 / 9.0));
             const R a1 = fmaR(R(-1.0 / 6.0), u2, R(1.0 / 9.0));
-            const R a5 = fmaR(R(-1.0 / 24.0), u2, R(1.0 / 36.0));
+            const R a5 = fmaR(R(1.0 / 12.0), u2, R(1.0 / 36.0));
             const R dx = fmaR(R(0.5), uxx, a1), dy = fmaR(R(0.5), uyy, a1);
-            const R dp = fmaR(R(0.125) * upv, upv, a5), dm = fmaR(R(0.125) * umv, umv, a5);
+            const R dp = fmaR(R(0.25), uxy, a5), dm = fmaR(R(-0.25), uxy, a5);
             R d[9];
-            d[0] = d0;
+            d[0] = fmaR(R(-2.0 / 3.0), u2, R(4.0 / 9.0));
             d[1] = fmaR(R(1.0 / 3.0), ux, dx);
             d[3] = fmaR(R(-1.0 / 3.0), ux, dx);
             d[2] = fmaR(R(1.0 / 3.0), uy, dy);

@@ -15,8 +15,10 @@ delta), Grad initialisation with unit density; turnover time t_c = N / u0 =
   vanishing dh and amplifies such differences (measured: about 2e-3 for A
   and 2e-5 for C after 400 steps); B, D and LBGK stay near 1e-11.
 * KBC-B at t = t_c: energy and enstrophy of the FP64 form match the oracle's
-  to 1e-9 relative; the FP32 form to 1e-3 (energy) and 1e-2 (enstrophy),
-  the proposed trace bounds for chaotic runs.
+  to 1e-9 relative, or to 100 times the oracle's own sensitivity of each
+  (same perturbed rerun) where that is larger: over 3200 steps rounding-order
+  differences alone move the enstrophy by about 1e-9.  The FP32 form: 1e-3
+  (energy) and 1e-2 (enstrophy), the proposed trace bounds for chaotic runs.
 * Every KBC variant stays finite to t_c at this resolution, where the paper
   reports KBC runs throughout; LBGK is run and reported, not asserted.
 """
@@ -82,9 +84,14 @@ def test_shear_layer_fp64_400_steps(orc, layer, coll, var):
 def test_shear_layer_kbc_b_to_turnover(orc, layer):
     ux, uy = layer
     p = oparams(orc, "kbc", "B")
-    fo = orc.run(p, orc.init(p, ux, uy), TC)
-    do = orc.diagnostics(p, fo)
-    for form, bE, bZ in (("f64", 1e-9, 1e-9), ("f32", 1e-3, 1e-2)):
+    f0 = orc.init(p, ux, uy)
+    do = orc.diagnostics(p, orc.run(p, f0, TC))
+    rng = np.random.default_rng(0)
+    dp = orc.diagnostics(p, orc.run(p, f0 * (1 + 1e-15 * rng.standard_normal(f0.shape)), TC))
+    sE = abs(dp["E"] - do["E"]) / do["E"]
+    sZ = abs(dp["Z"] - do["Z"]) / do["Z"]
+    say(f"  oracle self-sensitivity at t_c: E {sE:.2e}, Z {sZ:.2e}")
+    for form, bE, bZ in (("f64", max(1e-9, 100 * sE), max(1e-9, 100 * sZ)), ("f32", 1e-3, 1e-2)):
         s = Sim(N, N, BETA, collision="kbc", variant="B", form=form).init(ux, uy)
         s.step(TC)
         d = s.diagnostics()
