@@ -85,6 +85,8 @@ _SIGS = {
     "lbm_adjoint_segment": (_c.c_int, [_vp, _vp, _c.POINTER(_vp), _c.c_int32, _vp, _vp, _vp,
                                        _c.POINTER(_c.c_int32)]),
     "lbm_adjoint_init": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int32, _vp, _vp, _vp, _vp]),
+    "lbm_adjoint_rollout": (_c.c_int, [_vp, _c.POINTER(_vp), _c.c_int32, _c.c_int32, _c.POINTER(_vp),
+                                       _c.POINTER(_vp), _vp, _vp, _vp, _vp, _c.POINTER(_c.c_int32)]),
 }
 
 

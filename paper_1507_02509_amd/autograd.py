@@ -7,8 +7,10 @@ population state every K steps (K = ceil(sqrt(nsteps)) by default); the
 backward pass walks the segments from last to first, recomputes the K states
 of a segment from its checkpoint into K - 1 slots, and runs the hand-written
 adjoint step kernel back through them, then the adjoint of the initial state.
-Memory is about 2 sqrt(nsteps) states; the recomputation adds one forward
-step per step.
+By default (``overlap=True``) one native call runs all segments, recomputing
+the next segment on a second stream while the current one runs backward, with
+two slot sets.  Memory is about 2 sqrt(nsteps) states (3 with overlap); the
+recomputation adds one forward step per step.
 """
 from __future__ import annotations
 
@@ -32,6 +34,7 @@ class RolloutConfig:
     gamma_guard: float = 1e-12
     tile: tuple | None = None
     gamma_grad: str = "full"      # "full": differentiate gamma(f); "frozen": hold it
+    overlap: bool = True          # recompute the next segment on a second stream (two slot sets)
 
 
 class _Rollout(torch.autograd.Function):
@@ -67,11 +70,24 @@ class _Rollout(torch.autograd.Function):
         lam_a, lam_b = sim.new_adjoint(), sim.new_adjoint()
         acc = torch.zeros(1, dtype=torch.float64, device=dev)
         sim.adjoint_seed(ctx.final, lam_a, grho, gux, guy)
-        slots = [sim.new_state() for _ in range(max(0, min(K, N) - 1))]
-        for s in sorted(ctx.ckpts.keys(), reverse=True):
-            k = min(s + K, N) - s
-            if sim.adjoint_segment(ctx.ckpts[s], slots, k, lam_a, lam_b, acc):
+        nslot = max(0, min(K, N) - 1)
+        slots = [sim.new_state() for _ in range(nslot)]
+        if ctx.cfg.overlap and len(ctx.ckpts) > 1:
+            aux = torch.cuda.Stream(device=dev)
+            h = sim.params.stream                      # the context's stream (None: the null stream)
+            main = torch.cuda.ExternalStream(h, device=dev) if h else torch.cuda.current_stream(dev)
+            aux.wait_stream(main)
+            slots_b = [sim.new_state() for _ in range(nslot)]
+            ckpts = [ctx.ckpts[s] for s in sorted(ctx.ckpts.keys())]
+            for t in slots + slots_b + ckpts:
+                t.record_stream(aux)
+            if sim.adjoint_rollout(ckpts, N, K, slots, slots_b, lam_a, lam_b, acc, aux):
                 lam_a, lam_b = lam_b, lam_a
+        else:
+            for s in sorted(ctx.ckpts.keys(), reverse=True):
+                k = min(s + K, N) - s
+                if sim.adjoint_segment(ctx.ckpts[s], slots, k, lam_a, lam_b, acc):
+                    lam_a, lam_b = lam_b, lam_a
         gx = torch.empty_like(ux0)
         gy = torch.empty_like(uy0)
         sim.adjoint_init(ux0, uy0, lam_a, gx, gy, acc, mode=ctx.cfg.init)

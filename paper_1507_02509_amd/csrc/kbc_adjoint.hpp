@@ -6,8 +6,9 @@
 // the node's contribution mu . dg'/dbeta.  The stabiliser gamma(f) of
 // eq. (result21) is by default differentiated with the rest of the collision through
 // <ds|dh>, <dh|dh> and the entropic weights 1/feq; where the denominator guard
-// selects gamma = 2 it is a constant.  The forward quantities are recomputed
-// with exactly the operations of collide(), then the chain rule runs through
+// selects gamma = 2 it is a constant.  The forward quantities of the KBC
+// collision come from kbc_forward(), the code collide() runs, so both take the
+// same guard decisions on the same values; the chain rule then runs through
 // them in reverse order.
 #pragma once
 
@@ -35,26 +36,24 @@ __device__ __forceinline__ void pop_to_moments_adj(const R (&pb)[9], R& Tb, R& N
 template <typename R, int COLL, int VAR, int GM, bool FROZEN = false>
 __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], const Coef<R>& K,
                                             R (&lam)[9], R& dbeta) {
-    // ------------------------------------------------ forward (as in collide)
-    const R s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
-    const R d13 = g[1] - g[3], d24 = g[2] - g[4], d57 = g[5] - g[7], d68 = g[6] - g[8];
-    const R sd = s57 + s68;
-    const R dr = (g[0] + sd) + (s13 + s24);
-    const R jx = d13 + (d57 - d68);
-    const R jy = d24 + (d57 + d68);
-    const R rho = K.rho0 + dr;
-    const R ir = rcpR(rho);
-    const R ux = jx * ir, uy = jy * ir;
-    const R uxx = ux * ux, uyy = uy * uy, u2 = uxx + uyy;
-    const R upv = ux + uy, umv = ux - uy;
-
     // adjoints of rho - rho0, j and u collected below
     R drb = R(0), jxb = R(0), jyb = R(0), uxb = R(0), uyb = R(0);
     // adjoints of the raw sums of g: sum c_x^2 g, sum c_y^2 g, sum c_x c_y g,
     // sum c_x c_y^2 g, sum c_x^2 c_y g, sum c_x^2 c_y^2 g
     R Sxxb = R(0), Syyb = R(0), Sxyb = R(0), Qxrb = R(0), Qyrb = R(0), Arb = R(0);
+    R ir, ux, uy;
 
     if constexpr (COLL == LBGK) {
+        const R s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
+        const R d13 = g[1] - g[3], d24 = g[2] - g[4], d57 = g[5] - g[7], d68 = g[6] - g[8];
+        const R dr = (g[0] + (s57 + s68)) + (s13 + s24);
+        const R jx = d13 + (d57 - d68), jy = d24 + (d57 + d68);
+        const R rho = K.rho0 + dr;
+        ir = rcpR(rho);
+        ux = jx * ir;
+        uy = jy * ir;
+        const R uxx = ux * ux, uyy = uy * uy, u2 = uxx + uyy;
+        const R upv = ux + uy, umv = ux - uy;
         // g' = g - 2 beta (g - feqd); feqd_i = W_i [ (rho - rho0) + rho e_i ]
         const R c0 = R(-1.5) * u2;
         const R bx = fmaR(R(4.5), uxx, c0), by = fmaR(R(4.5), uyy, c0);
@@ -88,69 +87,19 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
         }
         dbeta = R(-2) * db;
     } else {
+        KbcNode<R> n;
+        kbc_forward<R, VAR, GM>(g, K, n);
         const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
-        const R jux = jx * ux, juy = jy * uy;
-        const R dr3 = dr * third;
-        const R dPxx = ((s13 + sd) - dr3) - jux;
-        const R dPyy = ((s24 + sd) - dr3) - juy;
-        const R dPxy = (s57 - s68) - jx * uy;
-        const R dQx = (d57 - d68) - jx * third;
-        const R dQy = (d57 + d68) - jy * third;
-        const R dA = (sd - dr * ninth) - (jux + juy) * third;
-        const R dT = dPxx + dPyy, dN = dPxx - dPyy, dP = dPxy;
-        R Ts, Qxs, Qys, As;
-        R tT = R(0);
-        if constexpr (VAR == VC) {
-            Ts = dT; Qxs = R(0); Qys = R(0); As = R(0);
-        } else if constexpr (VAR == VD) {
-            Ts = R(0); Qxs = R(0); Qys = R(0); As = R(0);
-        } else {
-            tT = (VAR == VA) ? dT : R(0);
-            const R hux = R(0.5) * ux, huy = R(0.5) * uy;
-            Ts = tT;
-            Qxs = fmaR(R(2) * uy, dP, hux * (tT - dN));
-            Qys = fmaR(R(2) * ux, dP, huy * (tT + dN));
-            As = fmaR(R(4) * ux * uy, dP, fmaR(R(0.5) * u2, tT, R(-0.5) * (uxx - uyy) * dN));
-        }
-        R ds[9], dh[9];
-        moments_to_pop<R>(Ts, dN, dP, Qxs, Qys, As, ds);
-        moments_to_pop<R>(dT - Ts, R(0), R(0), dQx - Qxs, dQy - Qys, dA - As, dh);
-
-        R gam = R(2), ratio = R(0), bsum = R(1);
-        bool active = false;          // gamma depends on f
-        R d[9], w[9];
-        if constexpr (GM == GFIX) {
-            gam = K.gamma_fixed;
-        } else {
-            const R d0 = fmaR(R(-2.0 / 3.0), u2, R(4.0 / 9.0));
-            const R a1 = fmaR(R(-1.0 / 6.0), u2, R(1.0 / 9.0));
-            const R a5 = fmaR(R(-1.0 / 24.0), u2, R(1.0 / 36.0));
-            const R dx = fmaR(R(0.5), uxx, a1), dy = fmaR(R(0.5), uyy, a1);
-            const R dp = fmaR(R(0.125) * upv, upv, a5), dm = fmaR(R(0.125) * umv, umv, a5);
-            d[0] = d0;
-            d[1] = fmaR(R(1.0 / 3.0), ux, dx);
-            d[3] = fmaR(R(-1.0 / 3.0), ux, dx);
-            d[2] = fmaR(R(1.0 / 3.0), uy, dy);
-            d[4] = fmaR(R(-1.0 / 3.0), uy, dy);
-            d[5] = fmaR(R(1.0 / 12.0), upv, dp);
-            d[7] = fmaR(R(-1.0 / 12.0), upv, dp);
-            d[8] = fmaR(R(1.0 / 12.0), umv, dm);
-            d[6] = fmaR(R(-1.0 / 12.0), umv, dm);
-            R a = R(0), b = R(0), c = R(0);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                w[i] = rcpR(d[i]);
-                const R wh = dh[i] * w[i];
-                a = fmaR(ds[i], wh, a);
-                b = fmaR(dh[i], wh, b);
-                c = fmaR(ds[i] * w[i], ds[i], c);
-            }
-            ratio = divR(a, b);
-            bsum = b;
-            const R gs = fmaR(-K.two_m_inv_beta, ratio, K.inv_beta);
-            active = !(b <= K.guard * c);
-            gam = active ? gs : R(2);
-        }
+        ir = n.ir;
+        ux = n.ux;
+        uy = n.uy;
+        const R jx = n.jx, jy = n.jy, uxx = n.uxx, uyy = n.uyy, u2 = n.u2;
+        const R dN = n.dN, dP = n.dP, tT = n.tT;
+        const R(&ds)[9] = n.ds;
+        const R(&dh)[9] = n.dh;
+        const R(&w)[9] = n.w;
+        const R gam = n.gam, ratio = n.ratio, bsum = n.b;
+        const bool active = n.active;
 
         // --------------------------------------------------------- reverse
         // (mul + add pairs below may fuse: nothing else is computed from
@@ -179,22 +128,29 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
                     const R rb = -K.two_m_inv_beta * gamb;     // adjoint of a / b
                     const R ab = rb * rcpR(bsum);              // adjoint of a
                     const R bb = -ab * ratio;                  // adjoint of b = -rb a / b^2
-                    R uxw = R(0), uyw = R(0);
+                    R wd[9];                                   // adjoint of d_i
     #pragma unroll
                     for (int i = 0; i < 9; ++i) {
-                        // a = sum ds dh w, b = sum dh dh w (c enters the guard only)
-                        dsb[i] = fmaR(ab * dh[i], w[i], dsb[i]);
-                        dhb[i] = fmaR(fmaR(ab, ds[i], R(2) * bb * dh[i]), w[i], dhb[i]);
-                        const R wb = dh[i] * fmaR(ab, ds[i], bb * dh[i]);
-                        const R dbar = -wb * w[i] * w[i];       // adjoint of d_i
-                        // d_i = W_i (1 - 1.5 |u|^2 + 4.5 (c.u)^2 + 3 c.u)
-                        const R cu = R(kCx[i]) * ux + R(kCy[i]) * uy;
-                        const R wd = R(weight(i)) * dbar;
-                        uxw = fmaR(wd, fmaR(R(9) * cu, R(kCx[i]), fmaR(R(-3), ux, R(3) * R(kCx[i]))), uxw);
-                        uyw = fmaR(wd, fmaR(R(9) * cu, R(kCy[i]), fmaR(R(-3), uy, R(3) * R(kCy[i]))), uyw);
+                        // a = sum ds dh w, b = sum dh dh w (c enters the guard only);
+                        // the adjoint of w_i is dh_i (ab ds_i + bb dh_i), w_i = 1 / d_i
+                        const R hw = dh[i] * w[i];
+                        const R bh = bb * dh[i];
+                        const R t = fmaR(ab, ds[i], bh);
+                        dsb[i] = fmaR(ab, hw, dsb[i]);
+                        dhb[i] = fmaR(t + bh, w[i], dhb[i]);
+                        wd[i] = -(hw * t) * w[i];
                     }
-                    uxb += uxw;
-                    uyb += uyw;
+                    // d_i in u: 4/9 - 2|u|^2/3; 1/9 - |u|^2/6 + u_a^2/2 +- u_a/3 (axes);
+                    // 1/36 + |u|^2/12 +- u_x u_y/4 + (c.u)/12 (diagonals)
+                    const R p57 = wd[5] + wd[7], p68 = wd[6] + wd[8];
+                    const R e0 = fmaR(R(1.0 / 6.0), p57 + p68, R(-4.0 / 3.0) * wd[0]);
+                    const R p13 = wd[1] + wd[3], p24 = wd[2] + wd[4];
+                    const R cx = fmaR(R(2.0 / 3.0), p13, fmaR(R(-1.0 / 3.0), p24, e0));
+                    const R cy = fmaR(R(-1.0 / 3.0), p13, fmaR(R(2.0 / 3.0), p24, e0));
+                    const R dq = R(0.25) * (p57 - p68);
+                    const R m57 = wd[5] - wd[7], m86 = wd[8] - wd[6];
+                    uxb += fmaR(ux, cx, fmaR(uy, dq, fmaR(R(1.0 / 3.0), wd[1] - wd[3], R(1.0 / 12.0) * (m57 + m86))));
+                    uyb += fmaR(uy, cy, fmaR(ux, dq, fmaR(R(1.0 / 3.0), wd[2] - wd[4], R(1.0 / 12.0) * (m57 - m86))));
                 }
             }
             // ds = P(Ts, dN, dP, Qxs, Qys, As), dh = P(dT - Ts, 0, 0, dQx - Qxs, dQy - Qys, dA - As)

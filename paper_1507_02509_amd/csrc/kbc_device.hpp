@@ -167,14 +167,27 @@ __device__ __forceinline__ R exact_gamma(R gam, const R (&ds)[9], const R (&dh)[
     return gam;
 }
 
-// One collision on the deviations g (in place).  Returns the gamma used.
-//
+// Forward quantities of one KBC collision at a node, shared by the step
+// (collide) and its adjoint (collide_vjp) so that both take the same
+// decisions on the same values.
+template <typename R> struct KbcNode {
+    R dr, rho, ir, jx, jy;              // rho - rho0, rho, 1 / rho, rho u
+    R ux, uy, uxx, uyy, u2;
+    R dT, dN, dP;                       // non-equilibrium T, N, Pi
+    R tT;                               // T of the shear part: dT (A, C) or 0 (B, D)
+    R ds[9], dh[9];                     // shear and higher-order parts of f - feq
+    R w[9];                             // rho / feq_i (entropic weights)
+    R ratio, b;                         // <ds|dh> / <dh|dh> and <dh|dh>
+    R gam;                              // stabiliser used (estimate, 2 when guarded, or fixed)
+    bool active;                        // gamma follows eq. (result21) (not guarded, not fixed)
+};
+
 // Written for instruction count: the kernels that call it issue one vector
 // instruction per operation here and are bound by that issue rate, so every
 // product-plus-sum is an explicit FMA (contraction is off) and scale factors
 // are folded into the moments before they are spread back to populations.
-template <typename R, int COLL, int VAR, int GM>
-__device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
+template <typename R, int VAR, int GM>
+__device__ __forceinline__ void kbc_forward(const R (&g)[9], const Coef<R>& K, KbcNode<R>& n) {
     // conserved moments, eq. (moments) restricted to the deviations
     const R s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
     const R d13 = g[1] - g[3], d24 = g[2] - g[4], d57 = g[5] - g[7], d68 = g[6] - g[8];
@@ -188,8 +201,157 @@ __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
     const R ux = jx * ir, uy = jy * ir;
     const R uxx = ux * ux, uyy = uy * uy, u2 = uxx + uyy;
     const R upv = ux + uy, umv = ux - uy;
+    n.dr = dr; n.rho = rho; n.ir = ir; n.jx = jx; n.jy = jy;
+    n.ux = ux; n.uy = uy; n.uxx = uxx; n.uyy = uyy; n.u2 = u2;
 
+    constexpr bool kCentral = (VAR == VA || VAR == VB);   // s in the co-moving frame, eq. (cm)
+    constexpr bool kTrace = (VAR == VA || VAR == VC);     // T belongs to s
+    // non-equilibrium moments of df = f - feq (feq of second order, c_s^2 = 1/3)
+    const R juy = jy * uy;
+    const R jsum = fmaR(jx, ux, juy);          // rho |u|^2
+    const R jdif = fmaR(jx, ux, -juy);         // rho (u_x^2 - u_y^2)
+    const R dT = fmaR(R(2), sd, sa) - fmaR(R(2.0 / 3.0), dr, jsum);
+    const R dN = (s13 - s24) - jdif;
+    const R dP = fmaR(-jx, uy, s57 - s68);
+    const R dQx = fmaR(R(-1.0 / 3.0), jx, mq);
+    const R dQy = fmaR(R(-1.0 / 3.0), jy, pq);
+    const R dA = fmaR(R(-1.0 / 3.0), jsum, fmaR(R(-1.0 / 9.0), dr, sd));
+    const R uxy = ux * uy;
+    n.dT = dT; n.dN = dN; n.dP = dP;
+    n.tT = kTrace ? dT : R(0);
+
+    // Shear part s, Table kbc_moment_grouping: (T_s, N, Pi, Q_xyy,s, Q_yxx,s,
+    // A_s), all scaled by 1/4 (tq, nq, pq4, xq, yq, aq).  Central variants
+    // take the linear part of eq. (cm) at the node's velocity.
+    const R nq = R(0.25) * dN, pq4 = R(0.25) * dP;
+    R xq = R(0), yq = R(0), aq = R(0);
+    if constexpr (kCentral) {
+        const R p2 = R(0.5) * dP, n8 = R(0.125) * dN;
+        if constexpr (kTrace) {
+            const R t8 = R(0.125) * dT;
+            xq = fmaR(uy, p2, ux * (t8 - n8));
+            yq = fmaR(ux, p2, uy * (t8 + n8));
+            aq = fmaR(uxy, dP, fmaR(u2, t8, -((uxx - uyy) * n8)));
+        } else {
+            xq = fmaR(uy, p2, -(ux * n8));
+            yq = fmaR(ux, p2, uy * n8);
+            aq = fmaR(uxy, dP, -((uxx - uyy) * n8));
+        }
+    }
+    // populations of s, eq. (momentsD2Q9) without mass and momentum
+    R (&ds)[9] = n.ds;
+    {
+        R tpn, tmn;                              // (T_s +- N) / 4
+        if constexpr (kTrace) {
+            const R tq = R(0.25) * dT;
+            tpn = tq + nq;
+            tmn = tq - nq;
+        } else {
+            tpn = nq;
+            tmn = -nq;
+        }
+        if constexpr (kCentral) {
+            ds[0] = kTrace ? fmaR(R(4), aq, -dT) : R(4) * aq;
+            ds[1] = fmaR(R(-2), xq + aq, tpn);
+            ds[3] = fmaR(R(2), xq - aq, tpn);
+            ds[2] = fmaR(R(-2), yq + aq, tmn);
+            ds[4] = fmaR(R(2), yq - aq, tmn);
+            const R ap = aq + pq4, am = aq - pq4, xp = xq + yq, xm = xq - yq;
+            ds[5] = ap + xp;
+            ds[7] = ap - xp;
+            ds[6] = am - xm;
+            ds[8] = am + xm;
+        } else {
+            ds[0] = kTrace ? -dT : R(0);
+            ds[1] = tpn;
+            ds[3] = tpn;
+            ds[2] = tmn;
+            ds[4] = tmn;
+            ds[5] = pq4;
+            ds[7] = pq4;
+            ds[6] = -pq4;
+            ds[8] = -pq4;
+        }
+    }
+    // higher-order part h = df - s: moments (T - T_s, 0, 0, dQ - Q_s, dA - A_s) / 4
+    R (&dh)[9] = n.dh;
+    {
+        const R xh = kCentral ? fmaR(R(0.25), dQx, -xq) : R(0.25) * dQx;
+        const R yh = kCentral ? fmaR(R(0.25), dQy, -yq) : R(0.25) * dQy;
+        const R ah = kCentral ? fmaR(R(0.25), dA, -aq) : R(0.25) * dA;
+        const R hp = xh + yh, hm = xh - yh;
+        dh[5] = ah + hp;
+        dh[7] = ah - hp;
+        dh[6] = ah - hm;
+        dh[8] = ah + hm;
+        if constexpr (kTrace) {
+            dh[0] = R(4) * ah;
+            dh[1] = R(-2) * (xh + ah);
+            dh[3] = R(2) * (xh - ah);
+            dh[2] = R(-2) * (yh + ah);
+            dh[4] = R(2) * (yh - ah);
+        } else {
+            const R th = R(0.25) * dT;
+            dh[0] = fmaR(R(4), ah, -dT);
+            dh[1] = fmaR(R(-2), xh + ah, th);
+            dh[3] = fmaR(R(2), xh - ah, th);
+            dh[2] = fmaR(R(-2), yh + ah, th);
+            dh[4] = fmaR(R(2), yh - ah, th);
+        }
+    }
+
+    if constexpr (GM == GFIX) {
+        n.gam = K.gamma_fixed;
+        n.active = false;
+        n.ratio = R(0);
+        n.b = R(1);
+    } else {
+        // entropic scalar products, weights 1 / (W_i (1 + e_i)) = rho / feq_i;
+        // d_i = W_i (1 + e_i) = W_i (1 - 1.5 |u|^2 + 4.5 (v.u)^2) + 3 W_i (v.u)
+        const R a1 = fmaR(R(-1.0 / 6.0), u2, R(1.0 / 9.0));
+        const R a5 = fmaR(R(1.0 / 12.0), u2, R(1.0 / 36.0));
+        const R dx = fmaR(R(0.5), uxx, a1), dy = fmaR(R(0.5), uyy, a1);
+        const R dp = fmaR(R(0.25), uxy, a5), dm = fmaR(R(-0.25), uxy, a5);
+        R d[9];
+        d[0] = fmaR(R(-2.0 / 3.0), u2, R(4.0 / 9.0));
+        d[1] = fmaR(R(1.0 / 3.0), ux, dx);
+        d[3] = fmaR(R(-1.0 / 3.0), ux, dx);
+        d[2] = fmaR(R(1.0 / 3.0), uy, dy);
+        d[4] = fmaR(R(-1.0 / 3.0), uy, dy);
+        d[5] = fmaR(R(1.0 / 12.0), upv, dp);
+        d[7] = fmaR(R(-1.0 / 12.0), upv, dp);
+        d[8] = fmaR(R(1.0 / 12.0), umv, dm);
+        d[6] = fmaR(R(-1.0 / 12.0), umv, dm);
+        R a = R(0), b = R(0), c = R(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            n.w[i] = rcpR(d[i]);
+            const R wh = dh[i] * n.w[i];
+            a = fmaR(ds[i], wh, a);
+            b = fmaR(dh[i], wh, b);
+            c = fmaR(ds[i] * n.w[i], ds[i], c);
+        }
+        n.ratio = divR(a, b);
+        n.b = b;
+        const R gs = fmaR(-K.two_m_inv_beta, n.ratio, K.inv_beta);
+        n.active = !(b <= K.guard * c);
+        n.gam = n.active ? gs : R(2);
+    }
+}
+
+// One collision on the deviations g (in place).  Returns the gamma used.
+template <typename R, int COLL, int VAR, int GM>
+__device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
     if constexpr (COLL == LBGK) {
+        const R s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
+        const R d13 = g[1] - g[3], d24 = g[2] - g[4], d57 = g[5] - g[7], d68 = g[6] - g[8];
+        const R dr = (g[0] + (s57 + s68)) + (s13 + s24);
+        const R jx = d13 + (d57 - d68), jy = d24 + (d57 + d68);
+        const R rho = K.rho0 + dr;
+        const R ir = rcpR(rho);
+        const R ux = jx * ir, uy = jy * ir;
+        const R uxx = ux * ux, uyy = uy * uy, u2 = uxx + uyy;
+        const R upv = ux + uy, umv = ux - uy;
         // f' = f - 2 beta (f - feq), eq. (LBGKmirr) in eq. (Egeneral):
         // g' = (1 - 2 beta) g + 2 beta W_i [(rho - rho0) + rho e_i],
         // e_i = 3 (v.u) + 4.5 (v.u)^2 - 1.5 |u|^2
@@ -216,141 +378,16 @@ __device__ __forceinline__ R collide(R (&g)[9], const Coef<R>& K) {
         }
         return R(2);
     } else {
-        constexpr bool kCentral = (VAR == VA || VAR == VB);   // s in the co-moving frame, eq. (cm)
-        constexpr bool kTrace = (VAR == VA || VAR == VC);     // T belongs to s
-        // non-equilibrium moments of df = f - feq (feq of second order, c_s^2 = 1/3)
-        const R juy = jy * uy;
-        const R jsum = fmaR(jx, ux, juy);          // rho |u|^2
-        const R jdif = fmaR(jx, ux, -juy);         // rho (u_x^2 - u_y^2)
-        const R dT = fmaR(R(2), sd, sa) - fmaR(R(2.0 / 3.0), dr, jsum);
-        const R dN = (s13 - s24) - jdif;
-        const R dP = fmaR(-jx, uy, s57 - s68);
-        const R dQx = fmaR(R(-1.0 / 3.0), jx, mq);
-        const R dQy = fmaR(R(-1.0 / 3.0), jy, pq);
-        const R dA = fmaR(R(-1.0 / 3.0), jsum, fmaR(R(-1.0 / 9.0), dr, sd));
-        const R uxy = ux * uy;
-
-        // Shear part s, Table kbc_moment_grouping: (T_s, N, Pi, Q_xyy,s, Q_yxx,s,
-        // A_s), all scaled by 1/4 (tq, nq, pq4, xq, yq, aq).  Central variants
-        // take the linear part of eq. (cm) at the node's velocity.
-        const R nq = R(0.25) * dN, pq4 = R(0.25) * dP;
-        R xq = R(0), yq = R(0), aq = R(0);
-        if constexpr (kCentral) {
-            const R p2 = R(0.5) * dP, n8 = R(0.125) * dN;
-            if constexpr (kTrace) {
-                const R t8 = R(0.125) * dT;
-                xq = fmaR(uy, p2, ux * (t8 - n8));
-                yq = fmaR(ux, p2, uy * (t8 + n8));
-                aq = fmaR(uxy, dP, fmaR(u2, t8, -((uxx - uyy) * n8)));
-            } else {
-                xq = fmaR(uy, p2, -(ux * n8));
-                yq = fmaR(ux, p2, uy * n8);
-                aq = fmaR(uxy, dP, -((uxx - uyy) * n8));
-            }
-        }
-        // populations of s, eq. (momentsD2Q9) without mass and momentum
-        R ds[9];
-        {
-            R tpn, tmn;                              // (T_s +- N) / 4
-            if constexpr (kTrace) {
-                const R tq = R(0.25) * dT;
-                tpn = tq + nq;
-                tmn = tq - nq;
-            } else {
-                tpn = nq;
-                tmn = -nq;
-            }
-            if constexpr (kCentral) {
-                ds[0] = kTrace ? fmaR(R(4), aq, -dT) : R(4) * aq;
-                ds[1] = fmaR(R(-2), xq + aq, tpn);
-                ds[3] = fmaR(R(2), xq - aq, tpn);
-                ds[2] = fmaR(R(-2), yq + aq, tmn);
-                ds[4] = fmaR(R(2), yq - aq, tmn);
-                const R ap = aq + pq4, am = aq - pq4, xp = xq + yq, xm = xq - yq;
-                ds[5] = ap + xp;
-                ds[7] = ap - xp;
-                ds[6] = am - xm;
-                ds[8] = am + xm;
-            } else {
-                ds[0] = kTrace ? -dT : R(0);
-                ds[1] = tpn;
-                ds[3] = tpn;
-                ds[2] = tmn;
-                ds[4] = tmn;
-                ds[5] = pq4;
-                ds[7] = pq4;
-                ds[6] = -pq4;
-                ds[8] = -pq4;
-            }
-        }
-        // higher-order part h = df - s: moments (T - T_s, 0, 0, dQ - Q_s, dA - A_s) / 4
-        R dh[9];
-        {
-            const R xh = kCentral ? fmaR(R(0.25), dQx, -xq) : R(0.25) * dQx;
-            const R yh = kCentral ? fmaR(R(0.25), dQy, -yq) : R(0.25) * dQy;
-            const R ah = kCentral ? fmaR(R(0.25), dA, -aq) : R(0.25) * dA;
-            const R hp = xh + yh, hm = xh - yh;
-            dh[5] = ah + hp;
-            dh[7] = ah - hp;
-            dh[6] = ah - hm;
-            dh[8] = ah + hm;
-            if constexpr (kTrace) {
-                dh[0] = R(4) * ah;
-                dh[1] = R(-2) * (xh + ah);
-                dh[3] = R(2) * (xh - ah);
-                dh[2] = R(-2) * (yh + ah);
-                dh[4] = R(2) * (yh - ah);
-            } else {
-                const R th = R(0.25) * dT;
-                dh[0] = fmaR(R(4), ah, -dT);
-                dh[1] = fmaR(R(-2), xh + ah, th);
-                dh[3] = fmaR(R(2), xh - ah, th);
-                dh[2] = fmaR(R(-2), yh + ah, th);
-                dh[4] = fmaR(R(2), yh - ah, th);
-            }
-        }
-
-        R gam;
-        if constexpr (GM == GFIX) {
-            gam = K.gamma_fixed;
-        } else {
-            // entropic scalar products, weights 1 / (W_i (1 + e_i)) = rho / feq_i;
-            // d_i = W_i (1 + e_i) = W_i (1 - 1.5 |u|^2 + 4.5 (v.u)^2) + 3 W_i (v.u)
-            const R a1 = fmaR(R(-1.0 / 6.0), u2, R(1.0 / 9.0));
-            const R a5 = fmaR(R(1.0 / 12.0), u2, R(1.0 / 36.0));
-            const R dx = fmaR(R(0.5), uxx, a1), dy = fmaR(R(0.5), uyy, a1);
-            const R dp = fmaR(R(0.25), uxy, a5), dm = fmaR(R(-0.25), uxy, a5);
-            R d[9];
-            d[0] = fmaR(R(-2.0 / 3.0), u2, R(4.0 / 9.0));
-            d[1] = fmaR(R(1.0 / 3.0), ux, dx);
-            d[3] = fmaR(R(-1.0 / 3.0), ux, dx);
-            d[2] = fmaR(R(1.0 / 3.0), uy, dy);
-            d[4] = fmaR(R(-1.0 / 3.0), uy, dy);
-            d[5] = fmaR(R(1.0 / 12.0), upv, dp);
-            d[7] = fmaR(R(-1.0 / 12.0), upv, dp);
-            d[8] = fmaR(R(1.0 / 12.0), umv, dm);
-            d[6] = fmaR(R(-1.0 / 12.0), umv, dm);
-            R a = R(0), b = R(0), c = R(0);
-            R w[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                w[i] = rcpR(d[i]);
-                const R wh = dh[i] * w[i];
-                a = fmaR(ds[i], wh, a);
-                b = fmaR(dh[i], wh, b);
-                c = fmaR(ds[i] * w[i], ds[i], c);
-            }
-            const R gs = fmaR(-K.two_m_inv_beta, divR(a, b), K.inv_beta);
-            const bool guarded = (b <= K.guard * c);
-            gam = guarded ? R(2) : gs;
-            if constexpr (GM == GEXACT) {
-                if (!guarded) gam = exact_gamma<R>(gs, ds, dh, w, ir, K);
-            }
+        KbcNode<R> n;
+        kbc_forward<R, VAR, (GM == GEXACT ? GEST : GM)>(g, K, n);
+        R gam = n.gam;
+        if constexpr (GM == GEXACT) {
+            if (n.active) gam = exact_gamma<R>(gam, n.ds, n.dh, n.w, n.ir, K);
         }
         // f' = f - beta (2 ds + gamma dh), eqs. (Egeneral), (ksh-mirror)
         const R tb = R(2) * K.beta, bg = K.beta * gam;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = fmaR(-bg, dh[i], fmaR(-tb, ds[i], g[i]));
+        for (int i = 0; i < 9; ++i) g[i] = fmaR(-bg, n.dh[i], fmaR(-tb, n.ds[i], g[i]));
         return gam;
     }
 }

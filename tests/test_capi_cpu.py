@@ -94,6 +94,9 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.lbm_step_count(None) == -1
     assert lib.lbm_free(None) == L.LBM_OK
     assert lib.lbm_copy_probe(None, None, 4, None) == L.LBM_EINVAL
+    which = ctypes.c_int32(-1)
+    assert lib.lbm_adjoint_rollout(None, None, 10, 3, None, None, None, None, None, None,
+                                   ctypes.byref(which)) == L.LBM_EINVAL
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

@@ -204,6 +204,28 @@ def test_checkpoint_interval_does_not_change_the_gradient():
             assert torch.equal(a, c)
 
 
+@pytest.mark.parametrize("form,nsteps,K", [("f32", 23, 4), ("f32", 40, 5), ("f64", 17, 3), ("f32", 9, 2)])
+def test_overlapped_backward_is_bitwise_identical(form, nsteps, K):
+    """The backward pass that recomputes the next segment on a second stream
+    (two slot sets, event-ordered) returns the gradients of the one that runs
+    the segments in turn on one stream, bit for bit (ragged last segments
+    included)."""
+    nx, ny = 70, 33
+    say("overlapped backward", form, nsteps, K)
+    ux0, uy0 = inputs.spectral(nx, 3, 0.05, seed=52, ny=ny)
+    grads = []
+    for overlap in (False, True):
+        u0x = torch.from_numpy(ux0).cuda().requires_grad_(True)
+        u0y = torch.from_numpy(uy0).cuda().requires_grad_(True)
+        b = torch.tensor(beta_from_nu(1e-4), dtype=torch.float64, device="cuda", requires_grad=True)
+        _, ux, uy = rollout(u0x, u0y, b, nsteps, form=form, checkpoint_every=K, overlap=overlap)
+        (0.5 * (ux ** 2 + uy ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        grads.append((u0x.grad.clone(), u0y.grad.clone(), b.grad.clone()))
+    for a, c in zip(grads[1], grads[0]):
+        assert torch.equal(a, c)
+
+
 def c5_setup():
     n = 512
     ux0, uy0 = inputs.spectral(n, 8, 0.05, seed=5)
