@@ -255,25 +255,22 @@ int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* la
 int lbm_adjoint_segment(lbm_ctx* c, const void* state0, void* const* slots, int32_t k, void* lam_in,
                         void* lam_out, double* dbeta, int32_t* which);
 
-/* The whole backward pass of a checkpointed rollout of nsteps steps, with the
- * recomputation of one segment overlapped with the adjoint steps of the next.
+/* The whole backward pass of a checkpointed rollout of nsteps steps.
  * ckpts[j] = f^{j seglen} for j = 0 .. ceil(nsteps / seglen) - 1 (population
- * buffers of this context's layout).  Segments run from last to first: the
- * states f^{s+1} .. f^{s+k-1} of segment j are recomputed into one slot set
- * (slots_a or slots_b, seglen - 1 buffers each, alternating) on aux_stream
- * while the context's stream runs the k adjoint steps of segment j + 1 out of
- * the other set; events order the two streams, so the result is the one of
- * calling lbm_adjoint_segment for every segment in turn, bit for bit.
- * lam_in holds dL/df^{nsteps} on entry; *which receives 0 if dL/df^0 ended in
- * lam_in, 1 if in lam_out; the steps' dL/dbeta are added to *dbeta (nullable).
- * aux_stream (a hipStream_t of default priority, not the context's stream)
- * carries only the recomputation; when the call returns LBM_OK all of its
- * work is ordered before the context's stream's later work.  On an error,
- * synchronise both streams before reusing any buffer.  Owns no buffer;
- * creates and releases four events per call. */
+ * buffers of this context's layout).  Segments run from last to first, their
+ * states f^{s+1} .. f^{s+k-1} held in one of two slot sets (slots_a, slots_b:
+ * seglen - 1 distinct buffers each, alternating between segments).  Each
+ * launch runs one adjoint step of segment j and, in the same grid, one
+ * forward step recomputing a state of segment j - 1 into the other set, so
+ * the recomputation costs no launches of its own and the two fill the chip
+ * together on small lattices.  The result is bitwise that of calling
+ * lbm_adjoint_segment for every segment in turn.  lam_in holds dL/df^{nsteps}
+ * on entry; *which receives 0 if dL/df^0 ended in lam_in, 1 if in lam_out;
+ * the steps' dL/dbeta are added to *dbeta (nullable).  Stream-ordered on the
+ * context's stream; owns no buffer. */
 int lbm_adjoint_rollout(lbm_ctx* c, const void* const* ckpts, int32_t nsteps, int32_t seglen,
                         void* const* slots_a, void* const* slots_b, void* lam_in, void* lam_out, double* dbeta,
-                        void* aux_stream, int32_t* which);
+                        int32_t* which);
 
 /* Adjoint of lbm_init for modes LBM_INIT_EQ and LBM_INIT_GRAD_CD: from
  * lam0 = dL/df^0 and the initial fields (rho nullable = rho0), writes

@@ -86,7 +86,7 @@ _SIGS = {
                                        _c.POINTER(_c.c_int32)]),
     "lbm_adjoint_init": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int32, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_rollout": (_c.c_int, [_vp, _c.POINTER(_vp), _c.c_int32, _c.c_int32, _c.POINTER(_vp),
-                                       _c.POINTER(_vp), _vp, _vp, _vp, _vp, _c.POINTER(_c.c_int32)]),
+                                       _c.POINTER(_vp), _vp, _vp, _vp, _c.POINTER(_c.c_int32)]),
 }
 
 

@@ -7,9 +7,9 @@ population state every K steps (K = ceil(sqrt(nsteps)) by default); the
 backward pass walks the segments from last to first, recomputes the K states
 of a segment from its checkpoint into K - 1 slots, and runs the hand-written
 adjoint step kernel back through them, then the adjoint of the initial state.
-By default (``overlap=True``) one native call runs all segments, recomputing
-the next segment on a second stream while the current one runs backward, with
-two slot sets.  Memory is about 2 sqrt(nsteps) states (3 with overlap); the
+By default (``overlap=True``) one native call runs all segments: each launch
+runs one adjoint step of the current segment and one recomputation step of
+the next, which uses a second slot set.  Memory is about 2 sqrt(nsteps) states (3 with overlap); the
 recomputation adds one forward step per step.
 """
 from __future__ import annotations
@@ -34,7 +34,7 @@ class RolloutConfig:
     gamma_guard: float = 1e-12
     tile: tuple | None = None
     gamma_grad: str = "full"      # "full": differentiate gamma(f); "frozen": hold it
-    overlap: bool = True          # recompute the next segment on a second stream (two slot sets)
+    overlap: bool = True          # recompute the next segment inside the adjoint launches (two slot sets)
 
 
 class _Rollout(torch.autograd.Function):
@@ -73,15 +73,9 @@ class _Rollout(torch.autograd.Function):
         nslot = max(0, min(K, N) - 1)
         slots = [sim.new_state() for _ in range(nslot)]
         if ctx.cfg.overlap and len(ctx.ckpts) > 1:
-            aux = torch.cuda.Stream(device=dev)
-            h = sim.params.stream                      # the context's stream (None: the null stream)
-            main = torch.cuda.ExternalStream(h, device=dev) if h else torch.cuda.current_stream(dev)
-            aux.wait_stream(main)
             slots_b = [sim.new_state() for _ in range(nslot)]
             ckpts = [ctx.ckpts[s] for s in sorted(ctx.ckpts.keys())]
-            for t in slots + slots_b + ckpts:
-                t.record_stream(aux)
-            if sim.adjoint_rollout(ckpts, N, K, slots, slots_b, lam_a, lam_b, acc, aux):
+            if sim.adjoint_rollout(ckpts, N, K, slots, slots_b, lam_a, lam_b, acc):
                 lam_a, lam_b = lam_b, lam_a
         else:
             for s in sorted(ctx.ckpts.keys(), reverse=True):

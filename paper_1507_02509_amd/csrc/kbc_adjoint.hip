@@ -89,18 +89,19 @@ __global__ __launch_bounds__(256) void k_adj_seed(const typename Form<FORM>::S* 
 constexpr int kAdjStrip = 32;
 constexpr int kFold = 2048;   // partials per k_fold workgroup
 
+// The adjoint step of workgroup index bidx (the 256 threads of the calling
+// workgroup must all call it: it holds a workgroup barrier).
 template <int FORM, int COLL, int VAR, int GM, bool FROZEN>
-__global__ __launch_bounds__(256) void k_adj_step(const typename Form<FORM>::S* __restrict__ state,
-                                                  const typename Form<FORM>::R* __restrict__ lin,
-                                                  typename Form<FORM>::R* __restrict__ lout, int nx,
-                                                  int ny, int64_t pitch, int ntx, int nty,
-                                                  Coef<typename Form<FORM>::R> K,
-                                                  double* __restrict__ partials) {
+__device__ __forceinline__ void adj_tile(const typename Form<FORM>::S* __restrict__ state,
+                                         const typename Form<FORM>::R* __restrict__ lin,
+                                         typename Form<FORM>::R* __restrict__ lout, int nx, int ny,
+                                         int64_t pitch, int ntx, int nty, const Coef<typename Form<FORM>::R>& K,
+                                         double* __restrict__ partials, unsigned bidx) {
     using F = Form<FORM>;
     using R = typename F::R;
     using S = typename F::S;
     constexpr int TW = 128, WR = 2;
-    const int xcd = static_cast<int>(blockIdx.x & 7u), u = static_cast<int>(blockIdx.x >> 3);
+    const int xcd = static_cast<int>(bidx & 7u), u = static_cast<int>(bidx >> 3);
     const int rpx = (nty + 7) >> 3;                            // tile rows per XCD
     const int row0 = xcd * rpx;
     const int rows = (nty - row0 < rpx) ? (nty - row0 > 0 ? nty - row0 : 0) : rpx;
@@ -158,7 +159,45 @@ __global__ __launch_bounds__(256) void k_adj_step(const typename Form<FORM>::S* 
         db = static_cast<double>(dbn);
     }
     const double s = block_sum(db);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    if (threadIdx.x == 0) partials[bidx] = s;
+}
+
+template <int FORM, int COLL, int VAR, int GM, bool FROZEN>
+__global__ __launch_bounds__(256) void k_adj_step(const typename Form<FORM>::S* __restrict__ state,
+                                                  const typename Form<FORM>::R* __restrict__ lin,
+                                                  typename Form<FORM>::R* __restrict__ lout, int nx,
+                                                  int ny, int64_t pitch, int ntx, int nty,
+                                                  Coef<typename Form<FORM>::R> K,
+                                                  double* __restrict__ partials) {
+    adj_tile<FORM, COLL, VAR, GM, FROZEN>(state, lin, lout, nx, ny, pitch, ntx, nty, K, partials, blockIdx.x);
+}
+
+// An adjoint step and, in the same grid, one forward step between two other
+// state buffers (src -> dst): the backward pass of a checkpointed rollout
+// recomputes the next segment's states this way, inside the launches of the
+// current segment's adjoint steps, so that the two fill the chip together on
+// lattices too small to fill it alone.  Workgroups below nadj (a multiple of
+// 8, so both parts keep their XCD banding) run the adjoint tile, the others
+// the forward step's 256 x 1 tiles (the per-node code of every tile shape is
+// the same, so the recomputed states are those of any forward step).
+template <int FORM, int COLL, int VAR, int GM, bool FROZEN>
+__global__ __launch_bounds__(256) void k_adj_step_fwd(const typename Form<FORM>::S* __restrict__ state,
+                                                      const typename Form<FORM>::R* __restrict__ lin,
+                                                      typename Form<FORM>::R* __restrict__ lout, int nx,
+                                                      int ny, int64_t pitch, int ntx, int nty,
+                                                      Coef<typename Form<FORM>::R> K,
+                                                      double* __restrict__ partials, unsigned nadj,
+                                                      const typename Form<FORM>::S* __restrict__ src,
+                                                      typename Form<FORM>::S* __restrict__ dst, int ntx_f,
+                                                      int ntiles_f, int per_xcd_f) {
+    if (blockIdx.x < nadj) {
+        adj_tile<FORM, COLL, VAR, GM, FROZEN>(state, lin, lout, nx, ny, pitch, ntx, nty, K, partials, blockIdx.x);
+        return;
+    }
+    const int b = static_cast<int>(blockIdx.x - nadj);
+    const int t = (b & 7) * per_xcd_f + (b >> 3);
+    if (t >= ntiles_f) return;
+    step_tile<FORM, COLL, VAR, GM, 4, 1, false>(src, dst, nx, ny, pitch, t % ntx_f, t / ntx_f, K);
 }
 
 // out[g] = sum of partials[g * kFold .. (g + 1) * kFold), in a fixed order
@@ -276,32 +315,50 @@ int64_t adj_slice_len(const Lattice& L) {
 template <int FORM, int COLL, int VAR, int GM>
 struct AdjStepOp {
     static int run(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                   double* slice, double* acc) {
+                   double* slice, double* acc, const void* fsrc, void* fdst) {
         if constexpr (GM == GEXACT) {
             return -5;   // the adjoint of the exact stabiliser is not built
         } else {
-            return go(L, state, lin, lout, partials, slice, acc);
+            return go(L, state, lin, lout, partials, slice, acc, fsrc, fdst);
         }
     }
-    static int go(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                  double* slice, double* acc) {
+    template <bool FROZEN>
+    static void launch(const Lattice& L, const void* state, const void* lin, void* lout, int ntx, int nty,
+                       int64_t nb, double* out, const void* fsrc, void* fdst) {
         using F = Form<FORM>;
         using R = typename F::R;
+        using S = typename F::S;
+        if (!fsrc) {
+            k_adj_step<FORM, COLL, VAR, GM, FROZEN><<<dim3(static_cast<unsigned>(nb)), dim3(256), 0, L.stream>>>(
+                static_cast<const S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx, L.ny, L.pitch,
+                ntx, nty, make_coef<R>(L), out);
+            return;
+        }
+        // forward part: 256 x 1 tiles, renumbered per XCD as in the step kernel
+        const int ntx_f = (L.nx + 255) / 256;
+        const int ntiles_f = ntx_f * L.ny;
+        const int per_xcd_f = (ntiles_f + 7) / 8;
+        const int64_t grid = nb + 8 * static_cast<int64_t>(per_xcd_f);
+        k_adj_step_fwd<FORM, COLL, VAR, GM, FROZEN><<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, L.stream>>>(
+            static_cast<const S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx, L.ny, L.pitch,
+            ntx, nty, make_coef<R>(L), out, static_cast<unsigned>(nb), static_cast<const S*>(fsrc),
+            static_cast<S*>(fdst), ntx_f, ntiles_f, per_xcd_f);
+    }
+    static int go(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
+                  double* slice, double* acc, const void* fsrc, void* fdst) {
         const int ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;
         const int64_t nb = adj_blocks(L);
         if (static_cast<int64_t>(ntx) * nty > (int64_t{1} << 30) || nb > (int64_t{1} << 31) - 1) return -1;
+        if ((fsrc == nullptr) != (fdst == nullptr)) return -1;
+        // the fused forward part needs its grid to fit next to the adjoint's
+        if (fsrc && (static_cast<int64_t>((L.nx + 255) / 256) * L.ny + 8 + nb > (int64_t{1} << 31) - 1)) return -1;
         const bool direct = nb <= kDirect;
         if (!slice || (!direct && !partials)) return -1;
         double* out = direct ? slice : partials;
-        const dim3 grid(static_cast<unsigned>(nb)), block(256);
         if (L.adj_frozen)
-            k_adj_step<FORM, COLL, VAR, GM, true><<<grid, block, 0, L.stream>>>(
-                static_cast<const typename F::S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx,
-                L.ny, L.pitch, ntx, nty, make_coef<R>(L), out);
+            launch<true>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
         else
-            k_adj_step<FORM, COLL, VAR, GM, false><<<grid, block, 0, L.stream>>>(
-                static_cast<const typename F::S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx,
-                L.ny, L.pitch, ntx, nty, make_coef<R>(L), out);
+            launch<false>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
         if (ok()) return -2;
         const int64_t len = adj_slice_len(L);
         if (!direct) {
@@ -364,8 +421,8 @@ int launch_adjoint_seed(const Lattice& L, const void* state, const double* drho,
 }
 
 int launch_adjoint_step(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                        double* slice, double* acc) {
-    return dispatch<AdjStepOp>(L, state, lin, lout, partials, slice, acc);
+                        double* slice, double* acc, const void* fsrc, void* fdst) {
+    return dispatch<AdjStepOp>(L, state, lin, lout, partials, slice, acc, fsrc, fdst);
 }
 
 int launch_adjoint_init(const Lattice& L, const double* rho, const double* ux, const double* uy, int mode,

@@ -456,7 +456,7 @@ int lbm_adjoint_segment(lbm_ctx* c, const void* state0, void* const* slots, int3
 
 int lbm_adjoint_rollout(lbm_ctx* c, const void* const* ckpts, int32_t nsteps, int32_t seglen,
                         void* const* slots_a, void* const* slots_b, void* lam_in, void* lam_out, double* dbeta,
-                        void* aux_stream, int32_t* which) {
+                        int32_t* which) {
     if (!c || !ckpts || nsteps < 1 || seglen < 1 || !lam_in || !lam_out || lam_in == lam_out || !which)
         return fail(LBM_EINVAL, "invalid adjoint rollout arguments");
     const int32_t nseg = (nsteps + seglen - 1) / seglen;
@@ -465,87 +465,48 @@ int lbm_adjoint_rollout(lbm_ctx* c, const void* const* ckpts, int32_t nsteps, in
     if (seglen > 1) {
         if (!slots_a || !slots_b) return fail(LBM_EINVAL, "two slot sets of seglen - 1 buffers are required");
         for (int32_t i = 0; i + 1 < seglen; ++i)
-            if (!slots_a[i] || !slots_b[i]) return fail(LBM_EINVAL, "slot %d is NULL", i);
+            if (!slots_a[i] || !slots_b[i] || slots_a[i] == slots_b[i])
+                return fail(LBM_EINVAL, "slot %d is NULL or shared by both sets", i);
     }
-    hipStream_t aux = static_cast<hipStream_t>(aux_stream);
-    if (aux == c->L.stream) return fail(LBM_EINVAL, "aux_stream must differ from the context's stream");
     const int64_t nb = kbc::adjoint_partials(c->L), ng = kbc::adjoint_slice_len(c->L);
     const int64_t kr = (static_cast<int64_t>(seglen) + 63) / 64 * 64;
     int rc = ensure_ascratch(c, static_cast<size_t>(nb + ng * kr + kr));
     if (rc) return rc;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};   // recomputed[2], consumed[2]
-    for (int i = 0; i < 4; ++i) {
-        hipError_t e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
-        if (e != hipSuccess) {
-            for (int q = 0; q < i; ++q) (void)hipEventDestroy(ev[q]);
-            return hip_fail(e, "adjoint rollout events");
-        }
-    }
     void* const* sets[2] = {slots_a, slots_b};
-    bool used[2] = {false, false};
-    kbc::Lattice La = c->L;
-    La.stream = aux;
     auto seg_len = [&](int32_t j) { return std::min(seglen, nsteps - j * seglen); };
-    // f^{s+1} .. f^{s+k-1} of segment j into slot set `set`, on the aux stream,
-    // once the adjoint steps that last read that set have finished
-    auto recompute = [&](int32_t j, int set) -> int {
-        if (used[set]) {
-            hipError_t e = hipStreamWaitEvent(aux, ev[2 + set], 0);
-            if (e != hipSuccess) return hip_fail(e, "adjoint rollout wait");
-        }
-        const int32_t k = seg_len(j);
-        for (int32_t i = 1; i < k; ++i) {
-            const void* src = (i == 1) ? ckpts[j] : sets[set][i - 2];
-            const int r = kbc::launch_step(La, src, sets[set][i - 1], c->shape);
-            if (r) return launch_result(r, "lbm_adjoint_rollout recompute");
-        }
-        hipError_t e = hipEventRecord(ev[set], aux);
-        return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint rollout record");
-    };
+    // source of recomputed state t + 1 (t = 0 .. k - 2) of segment j
+    auto fsrc = [&](int32_t j, int set, int32_t t) -> const void* { return t == 0 ? ckpts[j] : sets[set][t - 1]; };
+    // the last segment's states on their own
+    for (int32_t t = 0; t + 1 < seg_len(nseg - 1); ++t) {
+        const int r = kbc::launch_step(c->L, fsrc(nseg - 1, 0, t), sets[0][t], c->shape);
+        if (r) return launch_result(r, "lbm_adjoint_rollout recompute");
+    }
     void* a = lam_in;
     void* b = lam_out;
-    rc = recompute(nseg - 1, 0);
-    for (int32_t j = nseg - 1; j >= 0 && rc == LBM_OK; --j) {
-        const int set = (nseg - 1 - j) & 1;
-        // the next segment's states are rebuilt while this one runs backward
-        if (j > 0) {
-            rc = recompute(j - 1, set ^ 1);
-            if (rc) break;
-        }
-        hipError_t e = hipStreamWaitEvent(c->L.stream, ev[set], 0);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "adjoint rollout wait");
-            break;
-        }
+    for (int32_t j = nseg - 1; j >= 0; --j) {
+        const int set = (nseg - 1 - j) & 1, nxt = set ^ 1;
         const int32_t k = seg_len(j);
-        for (int32_t n = k - 1; n >= 0; --n) {
+        const int32_t kn = (j > 0) ? seg_len(j - 1) - 1 : 0;   // states to recompute for segment j - 1
+        // adjoint step t of the segment runs backward from n = k - 1; the
+        // same launch recomputes state t + 1 of segment j - 1 into the other
+        // slot set (read by nothing in this segment)
+        for (int32_t t = 0; t < k; ++t) {
+            const int32_t n = k - 1 - t;
             const void* st = (n == 0) ? ckpts[j] : sets[set][n - 1];
+            const bool fwd = t < kn;
             const int r = kbc::launch_adjoint_step(c->L, st, a, b, c->ascratch,
-                                                   c->ascratch + nb + static_cast<int64_t>(n) * ng, nullptr);
-            if (r) {
-                rc = launch_result(r, "lbm_adjoint_rollout");
-                break;
-            }
+                                                   c->ascratch + nb + static_cast<int64_t>(n) * ng, nullptr,
+                                                   fwd ? fsrc(j - 1, nxt, t) : nullptr, fwd ? sets[nxt][t] : nullptr);
+            if (r) return launch_result(r, "lbm_adjoint_rollout");
             std::swap(a, b);
         }
-        if (rc) break;
+        for (int32_t t = k; t < kn; ++t) {
+            const int r = kbc::launch_step(c->L, fsrc(j - 1, nxt, t), sets[nxt][t], c->shape);
+            if (r) return launch_result(r, "lbm_adjoint_rollout recompute");
+        }
         const int r = kbc::launch_sum_slices(c->ascratch + nb, ng, k, c->ascratch + nb + ng * kr, dbeta, c->L.stream);
-        if (r) {
-            rc = launch_result(r, "lbm_adjoint_rollout sum");
-            break;
-        }
-        e = hipEventRecord(ev[2 + set], c->L.stream);
-        if (e != hipSuccess) {
-            rc = hip_fail(e, "adjoint rollout record");
-            break;
-        }
-        used[set] = true;
+        if (r) return launch_result(r, "lbm_adjoint_rollout sum");
     }
-    // every recomputation is waited on by the main stream before its adjoint
-    // steps, so the main stream's completion implies the aux stream's;
-    // events are released once their pending work completes
-    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
-    if (rc) return rc;
     *which = (a == lam_in) ? 0 : 1;
     return LBM_OK;
 }

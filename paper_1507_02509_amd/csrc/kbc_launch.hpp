@@ -83,8 +83,10 @@ int64_t adjoint_slice_len(const Lattice& L);
 int launch_sum_slices(const double* slices, int64_t len, int k, double* tot, double* acc, hipStream_t stream);
 int launch_adjoint_seed(const Lattice& L, const void* state, const double* drho, const double* dux,
                         const double* duy, void* lam);
+// fsrc / fdst (both or neither): one forward step between two other state
+// buffers, run in the same launch as the adjoint step
 int launch_adjoint_step(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
-                        double* slice, double* acc);
+                        double* slice, double* acc, const void* fsrc = nullptr, void* fdst = nullptr);
 int launch_adjoint_init(const Lattice& L, const double* rho, const double* ux, const double* uy, int mode,
                         const void* lam0, double* gux, double* guy, double* P, double* partials,
                         int64_t nblocks_cap, double* acc);

@@ -201,19 +201,18 @@ class Sim:
                                              L.ptr(dbeta), ctypes.byref(which)), "lbm_adjoint_segment")
         return int(which.value)
 
-    def adjoint_rollout(self, ckpts, nsteps: int, seglen: int, slots_a, slots_b, lam_in, lam_out, dbeta,
-                        aux_stream) -> int:
+    def adjoint_rollout(self, ckpts, nsteps: int, seglen: int, slots_a, slots_b, lam_in, lam_out,
+                        dbeta=None) -> int:
         """The whole backward pass over checkpoints ckpts (f^0, f^seglen, ...),
-        recomputing each segment on aux_stream (a torch.cuda.Stream) while the
-        previous one runs backward (see lbm_adjoint_rollout); returns 0 if
-        dL/df^0 is in lam_in, 1 if in lam_out."""
+        each launch running one adjoint step and one recomputation step of the
+        next segment (see lbm_adjoint_rollout); returns 0 if dL/df^0 is in
+        lam_in, 1 if in lam_out."""
         def arr(ts):
             return (ctypes.c_void_p * max(1, len(ts)))(*[L.ptr(t) for t in ts]) if ts else None
         which = ctypes.c_int32(-1)
         L.check(self.lib.lbm_adjoint_rollout(self.ctx, arr(ckpts), int(nsteps), int(seglen), arr(slots_a),
                                              arr(slots_b), L.ptr(lam_in), L.ptr(lam_out), L.ptr(dbeta),
-                                             ctypes.c_void_p(aux_stream.cuda_stream), ctypes.byref(which)),
-                "lbm_adjoint_rollout")
+                                             ctypes.byref(which)), "lbm_adjoint_rollout")
         return int(which.value)
 
     def adjoint_init(self, ux0, uy0, lam0, grad_ux, grad_uy, dbeta=None, rho=None, mode: str = "grad_cd"):

@@ -95,7 +95,7 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.lbm_free(None) == L.LBM_OK
     assert lib.lbm_copy_probe(None, None, 4, None) == L.LBM_EINVAL
     which = ctypes.c_int32(-1)
-    assert lib.lbm_adjoint_rollout(None, None, 10, 3, None, None, None, None, None, None,
+    assert lib.lbm_adjoint_rollout(None, None, 10, 3, None, None, None, None, None,
                                    ctypes.byref(which)) == L.LBM_EINVAL
 
 

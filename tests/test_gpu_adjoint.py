@@ -204,12 +204,14 @@ def test_checkpoint_interval_does_not_change_the_gradient():
             assert torch.equal(a, c)
 
 
-@pytest.mark.parametrize("form,nsteps,K", [("f32", 23, 4), ("f32", 40, 5), ("f64", 17, 3), ("f32", 9, 2)])
+@pytest.mark.parametrize("form,nsteps,K", [("f32", 23, 4), ("f32", 40, 5), ("f64", 17, 3), ("f32", 9, 2),
+                                          ("f32", 21, 5)])
 def test_overlapped_backward_is_bitwise_identical(form, nsteps, K):
-    """The backward pass that recomputes the next segment on a second stream
-    (two slot sets, event-ordered) returns the gradients of the one that runs
-    the segments in turn on one stream, bit for bit (ragged last segments
-    included)."""
+    """The backward pass whose launches each run one adjoint step and one
+    recomputation step of the next segment (two slot sets) returns the
+    gradients of the one that recomputes and runs back each segment in turn,
+    bit for bit (ragged last segments included, shorter and longer than the
+    recomputation they share launches with)."""
     nx, ny = 70, 33
     say("overlapped backward", form, nsteps, K)
     ux0, uy0 = inputs.spectral(nx, 3, 0.05, seed=52, ny=ny)
