@@ -159,7 +159,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     // FP32 +38 %, FP64 +25 % for KBC-B at 16384^2); FP16 is limited by
     // arithmetic, which the ring of extra collisions only adds to
     c->fuse = 2;
-    c->fuse_rows = (p->form == LBM_F64) ? 8 : (p->form == LBM_F16DEV_F32 ? 24 : 16);
+    c->fuse_rows = (p->form == LBM_F64) ? 8 : 16;
     c->dscratch = nullptr;
     c->dscratch_elems = 0;
     c->ascratch = nullptr;

@@ -43,7 +43,7 @@ struct Step2Op {
     template <int TH>
     static int nt(const Lattice& L, const void* src, void* dst, int nt_flag) {
         // the LDS tile must fit the 160 KB of a CU
-        constexpr size_t lds = 9u * (TH + 2) * 66u * sizeof(typename Form<FORM>::S);
+        constexpr size_t lds = 9u * TH * 66u * sizeof(typename Form<FORM>::S);
         if constexpr (lds > 160u * 1024u) {
             return -1;
         } else {

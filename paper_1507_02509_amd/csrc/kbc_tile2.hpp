@@ -5,20 +5,27 @@
 // the larger ones only where the LDS tile fits a CU).  Step 1 runs on the
 // tile extended by one node on every side (66 x (TH + 2) nodes, periodic):
 // each node gathers its populations from the state buffer exactly as the
-// single step does (f_i at x - v_i), collides, and keeps the post-collision
-// values in LDS in the storage form.  Step 2 then gathers, for every output
-// node, population i from the LDS copy at x - v_i, collides and writes the
-// result to the destination buffer.  HBM traffic is the single step's 18
-// values per node for two steps; the ring of extra step-1 collisions costs
-// (66 (TH + 2)) / (64 TH) - 1 more arithmetic (16 % for TH = 16, 8 % for
-// TH = 32).  The values that pass through LDS are rounded to the storage
-// form exactly as the single step rounds them on the way to HBM, and both
-// steps run the same collision code, so two fused steps are bitwise
+// single step does (f_i at x - v_i) and collides.  It then pushes each
+// post-collision value, in the storage form, to where step 2 will read it:
+// population i of node e goes to slot e + v_i of population i's window, which
+// covers the 64 x TH output nodes plus one padding column on each side (a
+// value whose slot falls outside the window is not needed and not written).
+// Step 2 then reads, for every output node x, population i from slot x of
+// window i, collides and writes the result to the destination buffer.  The
+// windows take 9 x TH x 66 values of LDS instead of the extended tile's
+// 9 x (TH + 2) x 66 (FP32, TH = 16: 38.0 KB, four workgroups per CU instead
+// of three), and step 2's LDS reads are unshifted.  HBM traffic is the
+// single step's 18 values per node for two steps; the ring of extra step-1
+// collisions costs (66 (TH + 2)) / (64 TH) - 1 more arithmetic (16 % for
+// TH = 16, 8 % for TH = 32).  The values that pass through LDS are rounded to
+// the storage form exactly as the single step rounds them on the way to HBM,
+// and both steps run the same collision code, so two fused steps are bitwise
 // identical to two single steps.
 //
 // Work split: the 64 interior columns of every extended row are one wave
-// (lane = column), so the row is uniform across the wave and its bases are
-// scalar, as in the single step; the rows go to the four waves round-robin.
+// (lane = column), so the row is uniform across the wave, its bases are
+// scalar, as in the single step, and whether a population's slot row lies in
+// the window is a scalar branch; the rows go to the four waves round-robin.
 // The two halo columns (2 (TH + 2) nodes) go to the lanes of wave 3 (one
 // pass, two for TH = 32), with per-lane addressing.
 #pragma once
@@ -57,7 +64,7 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
     using R = typename F::R;
     using S = typename F::S;
     constexpr int TW = 64, EW = TW + 2, EH = TH + 2;
-    __shared__ S mid[9][EH][EW];
+    __shared__ S win[9][TH][EW];   // slot (row r, column c) holds output node (c - 1, r)
 
     const int lane = static_cast<int>(threadIdx.x & 63u);
     const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));   // wave index
@@ -91,8 +98,12 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
             for (int i = 0; i < 9; ++i) g[i] = F::dec(nxt[i], i);
             if (ey + 4 < EH) load_row(ey + 4, nxt);
             collide<R, COLL, VAR, GM>(g, K);
+            // node (lane, ey - 1) -> slot (lane + v_x + 1, ey - 1 + v_y); the row test is uniform
 #pragma unroll
-            for (int i = 0; i < 9; ++i) mid[i][ey][lane + 1] = F::enc(g[i], i);
+            for (int i = 0; i < 9; ++i) {
+                const int r = ey - 1 + kCy[i];
+                if (r >= 0 && r < TH) win[i][r][lane + 1 + kCx[i]] = F::enc(g[i], i);
+            }
         }
     }
     // ---- step 1, halo columns x0 - 1 and x0 + 64 (wrapped), every extended
@@ -110,9 +121,14 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
                 g[i] = F::dec(src[(static_cast<int64_t>(ys) * 9 + i) * pitch + xs], i);
             }
             collide<R, COLL, VAR, GM>(g, K);
-            const int ex = side ? EW - 1 : 0;
+            // node (-1 or 64, ey - 1): only the populations that move into
+            // the tile land in a column the output nodes read
 #pragma unroll
-            for (int i = 0; i < 9; ++i) mid[i][ey][ex] = F::enc(g[i], i);
+            for (int i = 0; i < 9; ++i) {
+                if (kCx[i] != (side ? -1 : 1)) continue;
+                const int r = ey - 1 + kCy[i];
+                if (r >= 0 && r < TH) win[i][r][side ? EW - 2 : 1] = F::enc(g[i], i);
+            }
         }
     }
     __syncthreads();
@@ -126,7 +142,7 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
         if (gx < nx) {
             R g[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] = F::dec(mid[i][oy + 1 - kCy[i]][lane + 1 - kCx[i]], i);
+            for (int i = 0; i < 9; ++i) g[i] = F::dec(win[i][oy][lane + 1], i);
             collide<R, COLL, VAR, GM>(g, K);
 #pragma unroll
             for (int i = 0; i < 9; ++i) st_at<NT>(row_ptr(dst, y, i, pitch), c0, F::enc(g[i], i));
