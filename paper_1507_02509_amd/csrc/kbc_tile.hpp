@@ -22,9 +22,20 @@ __device__ __forceinline__ S ld_at(const S* base, O off) {
 template <typename S>
 using gptr = __attribute__((address_space(1))) S*;
 
-template <bool NT, typename S, typename O>
-__device__ __forceinline__ void st_at(gptr<S> base, O off, S v) {
-    gptr<S> p = reinterpret_cast<gptr<S>>(reinterpret_cast<__attribute__((address_space(1))) char*>(base) + off);
+// A lane's 32-bit byte offset, made opaque where it is used: left alone, the
+// compiler hoists its widening to 64 bits out of the row loops, after which
+// base + offset no longer matches the scalar-base + 32-bit-offset address
+// form and every access pays a 64-bit vector add.  The empty statement emits
+// no instruction.
+__device__ __forceinline__ uint32_t lane_off(uint32_t off) {
+    asm("" : "+v"(off));
+    return off;
+}
+
+template <bool NT, typename S>
+__device__ __forceinline__ void st_at(gptr<S> base, uint32_t off, S v) {
+    gptr<S> p = reinterpret_cast<gptr<S>>(reinterpret_cast<__attribute__((address_space(1))) char*>(base) +
+                                          lane_off(off));
     if constexpr (NT)
         __builtin_nontemporal_store(v, p);
     else
@@ -53,10 +64,10 @@ __device__ __forceinline__ gptr<const S> row_ptr(const S* base, int y, int i, in
     return uniform_ptr(base + (static_cast<int64_t>(y) * 9 + i) * pitch);
 }
 
-template <typename S, typename O>
-__device__ __forceinline__ S ld_at(gptr<const S> base, O off) {
+template <typename S>
+__device__ __forceinline__ S ld_at(gptr<const S> base, uint32_t off) {
     return *reinterpret_cast<gptr<const S>>(reinterpret_cast<__attribute__((address_space(1))) const char*>(base) +
-                                            off);
+                                            lane_off(off));
 }
 
 // Tile (tx, ty) of a lattice: 64 * TXW nodes wide, (4 / TXW) * RPT rows tall,
