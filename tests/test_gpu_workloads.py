@@ -113,3 +113,53 @@ def test_c4_members_vs_oracle(orc):
         err = max(field_err(gx, ox), field_err(gy, oy))
         say(f"  c4 member {i}: n={n} nu={nu:.2e} seed={seed}: u err {err:.3e}")
         assert err < 1e-4
+
+
+def test_c2_long_run_all_models():
+    """The c2 workload over 10^4 steps (1024^2, nu = 1e-5, seed 2): every KBC
+    model and LBGK in FP32 and KBC-B in FP64, with E and Z every 50 steps.
+    Pointwise parity with the oracle is the 200-step test above; over 10^4
+    steps the flow decorrelates, so the FP32 KBC-B traces are held to the
+    proposed statistical bounds against the FP64 run: |dE| / E(0) <= 1e-3 and
+    |dZ| / Z(0) <= 1e-2 at every sample.  Every KBC model stays finite (the
+    paper reports no instability in any KBC run); the spatial mean of gamma of
+    KBC-B stays within 10 % of 1 (its stabiliser sits near the regularised
+    value, section on the entropic stabiliser); LBGK's first non-finite step,
+    if any, is printed, not asserted."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    steps, every = 10000, 50
+    ux, uy = inputs.spectral(N2, 8, 0.05, seed=SEED2)
+    beta = beta_from_nu(NU2)
+
+    def trace(coll, var, form):
+        s = Sim(N2, N2, beta, collision=coll, variant=var, form=form).init(ux, uy)
+        out, blown = [s.diagnostics()], None
+        for k in range(steps // every):
+            s.step(every)
+            d = s.diagnostics()
+            out.append(d)
+            if d["n_nonfinite"] and blown is None:
+                blown = (k + 1) * every
+                break
+        return out, blown
+
+    ref, blown = trace("kbc", "B", "f64")
+    assert blown is None
+    e0, z0 = ref[0]["E"], ref[0]["Z"]
+    for coll, var in [("kbc", "A"), ("kbc", "B"), ("kbc", "C"), ("kbc", "D"), ("lbgk", "A")]:
+        tr, blown = trace(coll, var, "f32")
+        if coll == "lbgk":
+            say(f"  c2 long run LBGK f32: first non-finite sample at step {blown}" if blown
+                else f"  c2 long run LBGK f32: finite to step {steps}, E {tr[-1]['E']:.5e}")
+            continue
+        assert blown is None, (var, blown)
+        g = np.mean([d["gamma"] for d in tr[1:]])
+        msg = f"  c2 long run KBC-{var} f32: E {tr[-1]['E']:.5e} Z {tr[-1]['Z']:.5e} mean gamma {g:.4f}"
+        if var == "B":
+            de = max(abs(a["E"] - b["E"]) for a, b in zip(tr, ref)) / e0
+            dz = max(abs(a["Z"] - b["Z"]) for a, b in zip(tr, ref)) / z0
+            msg += f"; vs FP64 max |dE|/E0 {de:.2e} |dZ|/Z0 {dz:.2e}"
+            assert de <= 1e-3 and dz <= 1e-2
+            assert abs(g - 1.0) < 0.1
+        say(msg)
