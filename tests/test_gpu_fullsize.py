@@ -99,3 +99,55 @@ def test_fullsize_one_step_sampled(orc, field, form):
     say("  samples", len(pts), "err", err)
     assert np.isfinite(fg).all()
     assert err < TOL[form]
+
+
+def oracle_window(orc, ux, uy, beta, x, y, nsteps):
+    """f^nsteps at (x, y) from the oracle run on a periodic window of half-width
+    nsteps + 2 cut from the full field around (x, y).  After n steps a node
+    depends on the initial velocity within distance n + 1 (n streaming steps
+    and the central-difference gradient of Grad's state); the window's own
+    wrap-around spreads inward one node per step from its edge, so its centre
+    is exact."""
+    h = nsteps + 2
+    d = np.arange(-h, h + 1)
+    iy = torch.as_tensor((y + d) % N, device=ux.device)[:, None]
+    ix = torch.as_tensor((x + d) % N, device=ux.device)[None, :]
+    pu = np.ascontiguousarray(ux[iy, ix].cpu().numpy())
+    pv = np.ascontiguousarray(uy[iy, ix].cpu().numpy())
+    p = orc.Params(2 * h + 1, 2 * h + 1, beta, collision=orc.KBC, variant=orc.VARIANTS["B"], threads=4)
+    f = orc.run(p, orc.init(p, pu, pv), nsteps)
+    return f[:, h, h]
+
+
+MULTI_TOL = {"f64": 1e-12, "f32": 1e-4, "f16": 1e-2}
+
+
+@pytest.mark.parametrize("form", ["f32", "f64", "f16"])
+def test_fullsize_steps_10_and_50_sampled(orc, field, form):
+    """As the one-step test, after 10 and 50 steps of the full lattice in the
+    default launch configuration (two fused steps per launch), against the
+    oracle on windows around 12 sampled nodes (corners, edges, random).
+    Bars (max |gpu - oracle| / max |oracle - W| over the samples): FP64 1e-12,
+    FP32 1e-4, FP16 1e-2 (binary16 rounding of every stored deviation, about
+    5e-4 of its size, over up to 50 steps)."""
+    ux, uy = field
+    beta = beta_from_nu(NU)
+    say("full-size steps 10 and 50", form)
+    pts = sample_nodes()[:8] + sample_nodes()[-4:]
+    xs = torch.as_tensor([q[0] for q in pts], device="cuda")
+    ys = torch.as_tensor([q[1] for q in pts], device="cuda")
+    s = Sim(N, N, beta, collision="kbc", variant="B", form=form).init(ux, uy)
+    done = 0
+    for nsteps in (10, 50):
+        s.step(nsteps - done)
+        done = nsteps
+        torch.cuda.synchronize()
+        f = s.get_populations()
+        fg = f[:, ys, xs].cpu().numpy().T
+        del f
+        torch.cuda.empty_cache()
+        fo = np.array([oracle_window(orc, ux, uy, beta, x, y, nsteps) for x, y in pts])
+        err = np.abs(fg - fo).max() / np.abs(fo - W).max()
+        say(f"  {form} after {nsteps} steps: samples {len(pts)}, err {err:.3e} (bar {MULTI_TOL[form]:.0e})")
+        assert np.isfinite(fg).all()
+        assert err < MULTI_TOL[form]
