@@ -487,3 +487,45 @@ def test_storage_forms_against_stored_oracle(orc, form):
         e_64 = pop_err(fg, orc.run(p, f0, steps))
         say(f"  {form} steps {steps}: vs stored oracle {e_st:.3e}, vs FP64 oracle {e_64:.3e}")
         assert e_st < bars[steps]
+
+
+@pytest.mark.parametrize("case", ["beta_one", "beta_small", "fixed_two", "fixed_regularised", "rho0"])
+def test_edge_parameters_f64(orc, case):
+    """The edges of the parameter space the boundary accepts, FP64, 10 steps
+    against the oracle in the same configuration (1e-12): beta = 1 (zero
+    viscosity), beta = 0.05 (strongly viscous), the fixed stabiliser gamma = 2
+    (which must also equal LBGK) and gamma = 1/beta (the regularised model), and
+    a reference density rho0 = 1.3 for the deviation storage (populations of
+    density about 1.3)."""
+    nx, ny, nsteps = 67, 45, 10
+    var, beta, gm, gfix, rho0, scale = "B", 0.97, "estimate", 2.0, 1.0, 1.0
+    if case == "beta_one":
+        beta = 1.0
+    elif case == "beta_small":
+        beta = 0.05
+    elif case == "fixed_two":
+        var, gm, gfix = "A", "fixed", 2.0
+    elif case == "fixed_regularised":
+        var, gm, gfix = "C", "fixed", 1.0 / beta
+    else:
+        rho0, scale = 1.3, 1.3
+    say("edge parameters", case)
+    f0 = random_state(orc, nx, ny, beta, seed=80) * scale
+    s = Sim(nx, ny, beta, collision="kbc", variant=var, form="f64", gamma_mode=gm, gamma_fixed=gfix, rho0=rho0)
+    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    s.set_populations(f0)
+    s.step(nsteps)
+    fg = s.get_populations().cpu().numpy()
+    p = orc_params(orc, nx, ny, beta, "kbc", var,
+                   gamma_mode=orc.GAMMA_FIXED if gm == "fixed" else orc.GAMMA_ESTIMATE, gamma_fixed=gfix)
+    fo = orc.run(p, f0, nsteps)
+    w = W * rho0
+    err = max(rel_err(fg[i], fo[i], sub=w[i]) for i in range(9))
+    say("  err", err)
+    assert np.isfinite(fg).all() and err < 1e-12
+    if case == "fixed_two":
+        lb = Sim(nx, ny, beta, collision="lbgk", form="f64")
+        lb.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+        lb.set_populations(f0)
+        lb.step(nsteps)
+        assert pop_err(fg, lb.get_populations().cpu().numpy()) < 1e-12
