@@ -204,23 +204,26 @@ def test_checkpoint_interval_does_not_change_the_gradient():
             assert torch.equal(a, c)
 
 
-@pytest.mark.parametrize("form,nsteps,K", [("f32", 23, 4), ("f32", 40, 5), ("f64", 17, 3), ("f32", 9, 2),
-                                          ("f32", 21, 5)])
-def test_overlapped_backward_is_bitwise_identical(form, nsteps, K):
+@pytest.mark.parametrize("form,nsteps,K,kw", [("f32", 23, 4, {}), ("f32", 40, 5, {}), ("f64", 17, 3, {}),
+                                             ("f32", 9, 2, {}), ("f32", 21, 5, {}),
+                                             ("f32", 23, 4, {"gamma_grad": "frozen"}),
+                                             ("f64", 19, 4, {"collision": "lbgk"}),
+                                             ("f32", 19, 4, {"variant": "D", "gamma_guard": 1e-4})])
+def test_overlapped_backward_is_bitwise_identical(form, nsteps, K, kw):
     """The backward pass whose launches each run one adjoint step and one
     recomputation step of the next segment (two slot sets) returns the
     gradients of the one that recomputes and runs back each segment in turn,
     bit for bit (ragged last segments included, shorter and longer than the
     recomputation they share launches with)."""
     nx, ny = 70, 33
-    say("overlapped backward", form, nsteps, K)
+    say("overlapped backward", form, nsteps, K, kw)
     ux0, uy0 = inputs.spectral(nx, 3, 0.05, seed=52, ny=ny)
     grads = []
     for overlap in (False, True):
         u0x = torch.from_numpy(ux0).cuda().requires_grad_(True)
         u0y = torch.from_numpy(uy0).cuda().requires_grad_(True)
         b = torch.tensor(beta_from_nu(1e-4), dtype=torch.float64, device="cuda", requires_grad=True)
-        _, ux, uy = rollout(u0x, u0y, b, nsteps, form=form, checkpoint_every=K, overlap=overlap)
+        _, ux, uy = rollout(u0x, u0y, b, nsteps, form=form, checkpoint_every=K, overlap=overlap, **kw)
         (0.5 * (ux ** 2 + uy ** 2).sum()).backward()
         torch.cuda.synchronize()
         grads.append((u0x.grad.clone(), u0y.grad.clone(), b.grad.clone()))
