@@ -541,6 +541,8 @@ struct lbm_ens {
     int rows;                   // fused tile height: 8 or 16
     kbc::EnsEntry* dtab2;       // member table for fused 64 x rows tiles
     int ntiles2;
+    int32_t* dmap2;             // member of each fused tile (one scalar load per workgroup)
+    int64_t dmap2_len;
 };
 
 namespace {
@@ -599,6 +601,29 @@ int ens_build(lbm_ens* e) {
     int rc = ens_upload(e, &e->dtab2, tab);
     if (rc) return rc;
     e->ntiles2 = static_cast<int>(tiles2);
+    {
+        std::vector<int32_t> map(static_cast<size_t>(tiles2));
+        for (size_t r = 0; r < tab.size(); ++r) {
+            const int64_t end = (r + 1 < tab.size()) ? tab[r + 1].tile_start : tiles2;
+            for (int64_t t = tab[r].tile_start; t < end; ++t) map[static_cast<size_t>(t)] = static_cast<int32_t>(r);
+        }
+        hipError_t err = hipStreamSynchronize(e->L.stream);
+        if (err != hipSuccess) return hip_fail(err, "ensemble tile map");
+        if (e->dmap2 && e->dmap2_len != tiles2) {
+            (void)hipFree(e->dmap2);
+            e->dmap2 = nullptr;
+        }
+        if (!e->dmap2) {
+            err = hipMalloc(&e->dmap2, static_cast<size_t>(tiles2 > 0 ? tiles2 : 1) * sizeof(int32_t));
+            if (err != hipSuccess) {
+                e->dmap2 = nullptr;
+                return fail(LBM_ENOMEM, "ensemble tile map: %s", hipGetErrorString(err));
+            }
+            e->dmap2_len = tiles2;
+        }
+        err = hipMemcpy(e->dmap2, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (err != hipSuccess) return hip_fail(err, "ensemble tile map upload");
+    }
     ens_table(e, e->shape.width, (256 / e->shape.width) * e->shape.rpt, tab);
     rc = ens_upload(e, &e->dtab, tab);
     if (rc) return rc;
@@ -638,6 +663,8 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
     }
     e->dtab = nullptr;
     e->dtab2 = nullptr;
+    e->dmap2 = nullptr;
+    e->dmap2_len = 0;
     e->blocks = 0;
     // two fused steps per launch where the single lattice uses them
     e->fuse = (m0->p.form == LBM_F16DEV_F32) ? 1 : 2;
@@ -646,6 +673,7 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
     if (rc) {
         if (e->dtab) (void)hipFree(e->dtab);
         if (e->dtab2) (void)hipFree(e->dtab2);
+        if (e->dmap2) (void)hipFree(e->dmap2);
         delete e;
         return rc;
     }
@@ -690,6 +718,7 @@ int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent) {
     int par = cur;
     if (pairs) {
         a.table = e->dtab2;
+        a.tile_member = e->dmap2;
         a.ntiles = e->ntiles2;
         a.nsteps = pairs;
         a.parity = par;
@@ -735,11 +764,12 @@ int lbm_ensemble_get_fusion(const lbm_ens* e, int32_t* rows) {
 int lbm_ensemble_free(lbm_ens* e) {
     if (!e) return LBM_OK;
     int rc = LBM_OK;
-    if (e->dtab || e->dtab2) {
+    if (e->dtab || e->dtab2 || e->dmap2) {
         hipError_t err = hipStreamSynchronize(e->L.stream);
         if (err != hipSuccess) rc = hip_fail(err, "lbm_ensemble_free sync");
         if (e->dtab) (void)hipFree(e->dtab);
         if (e->dtab2) (void)hipFree(e->dtab2);
+        if (e->dmap2) (void)hipFree(e->dmap2);
     }
     delete e;
     return rc;

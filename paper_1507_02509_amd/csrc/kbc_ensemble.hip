@@ -67,21 +67,20 @@ __global__ __launch_bounds__(256) void k_ens(const EnsEntry* __restrict__ tab, i
     }
 }
 
+// The member of tile t comes from a per-tile index (one scalar load) rather
+// than a binary search over the table, whose dependent loads would stall
+// every workgroup at its start.
 template <int FORM, int COLL, int VAR, int GM, int TH, bool NT>
-__global__ __launch_bounds__(256) void k_ens2(const EnsEntry* __restrict__ tab, int nmem, int ntiles,
-                                              int per_xcd, int parity) {
+__global__ __launch_bounds__(256) void k_ens2(const EnsEntry* __restrict__ tab,
+                                              const int32_t* __restrict__ tile_member, int ntiles, int per_xcd,
+                                              int parity) {
     using F = Form<FORM>;
     using S = typename F::S;
     using R = typename F::R;
     const int b = blockIdx.x;
     const int t = (b & 7) * per_xcd + (b >> 3);
     if (t >= ntiles) return;   // the whole workgroup leaves together
-    int lo = 0, hi = nmem - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab[mid].tile_start <= t) lo = mid; else hi = mid - 1;
-    }
-    const EnsEntry& e = tab[lo];
+    const EnsEntry& e = tab[tile_member[t]];
     Coef<R> K;
     K.beta = static_cast<R>(e.beta);
     K.inv_beta = static_cast<R>(e.inv_beta);
@@ -103,7 +102,7 @@ struct Ens2Op {
         for (int s = 0; s < a.nsteps; ++s) {
             const int par = (a.parity + s) & 1;
             k_ens2<FORM, COLL, VAR, GM, TH, NT><<<dim3(8u * static_cast<unsigned>(per_xcd)), dim3(256), 0, a.stream>>>(
-                a.table, a.nmem, a.ntiles, per_xcd, par);
+                a.table, a.tile_member, a.ntiles, per_xcd, par);
             if (hipGetLastError() != hipSuccess) return -2;
         }
         return 0;
@@ -113,6 +112,7 @@ struct Ens2Op {
         if constexpr (GM == GEXACT) {
             return -5;
         } else {
+            if (!a.tile_member) return -1;
             switch (a.rows * 2 + (a.shape.nt ? 1 : 0)) {
                 case 8 * 2: return go<8, false>(a);
                 case 8 * 2 + 1: return go<8, true>(a);

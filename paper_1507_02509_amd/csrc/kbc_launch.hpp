@@ -65,6 +65,7 @@ struct EnsLaunch {
     hipStream_t stream;
     int* query_blocks;      // if set: only report the resident-workgroup count
     int rows;               // fused launches: output tile height (8 or 16)
+    const int32_t* tile_member;   // fused launches: member of each tile (device)
 };
 int launch_ensemble(const Lattice& L, const EnsLaunch& a);
 // two fused steps per launch for every member; a.nsteps counts launches, the
