@@ -543,6 +543,8 @@ struct lbm_ens {
     int ntiles2;
     int32_t* dmap2;             // member of each fused tile (one scalar load per workgroup)
     int64_t dmap2_len;
+    int32_t* dmap;              // member of each single-step tile
+    int64_t dmap_len;
 };
 
 namespace {
@@ -593,6 +595,32 @@ int ens_upload(lbm_ens* e, kbc::EnsEntry** dst, const std::vector<kbc::EnsEntry>
     return LBM_OK;
 }
 
+// Member index of every tile of a table (tiles in member order), uploaded to
+// *dst, which is reallocated when the tile count changes.
+int ens_map(lbm_ens* e, const std::vector<kbc::EnsEntry>& tab, int64_t tiles, int32_t** dst, int64_t* len) {
+    std::vector<int32_t> map(static_cast<size_t>(tiles));
+    for (size_t r = 0; r < tab.size(); ++r) {
+        const int64_t end = (r + 1 < tab.size()) ? tab[r + 1].tile_start : tiles;
+        for (int64_t t = tab[r].tile_start; t < end; ++t) map[static_cast<size_t>(t)] = static_cast<int32_t>(r);
+    }
+    hipError_t err = hipStreamSynchronize(e->L.stream);
+    if (err != hipSuccess) return hip_fail(err, "ensemble tile map");
+    if (*dst && *len != tiles) {
+        (void)hipFree(*dst);
+        *dst = nullptr;
+    }
+    if (!*dst) {
+        err = hipMalloc(dst, static_cast<size_t>(tiles > 0 ? tiles : 1) * sizeof(int32_t));
+        if (err != hipSuccess) {
+            *dst = nullptr;
+            return fail(LBM_ENOMEM, "ensemble tile map: %s", hipGetErrorString(err));
+        }
+        *len = tiles;
+    }
+    err = hipMemcpy(*dst, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    return err == hipSuccess ? LBM_OK : hip_fail(err, "ensemble tile map upload");
+}
+
 int ens_build(lbm_ens* e) {
     std::vector<kbc::EnsEntry> tab;
     const int64_t tiles = ens_table(e, e->shape.width, (256 / e->shape.width) * e->shape.rpt, tab);
@@ -601,31 +629,12 @@ int ens_build(lbm_ens* e) {
     int rc = ens_upload(e, &e->dtab2, tab);
     if (rc) return rc;
     e->ntiles2 = static_cast<int>(tiles2);
-    {
-        std::vector<int32_t> map(static_cast<size_t>(tiles2));
-        for (size_t r = 0; r < tab.size(); ++r) {
-            const int64_t end = (r + 1 < tab.size()) ? tab[r + 1].tile_start : tiles2;
-            for (int64_t t = tab[r].tile_start; t < end; ++t) map[static_cast<size_t>(t)] = static_cast<int32_t>(r);
-        }
-        hipError_t err = hipStreamSynchronize(e->L.stream);
-        if (err != hipSuccess) return hip_fail(err, "ensemble tile map");
-        if (e->dmap2 && e->dmap2_len != tiles2) {
-            (void)hipFree(e->dmap2);
-            e->dmap2 = nullptr;
-        }
-        if (!e->dmap2) {
-            err = hipMalloc(&e->dmap2, static_cast<size_t>(tiles2 > 0 ? tiles2 : 1) * sizeof(int32_t));
-            if (err != hipSuccess) {
-                e->dmap2 = nullptr;
-                return fail(LBM_ENOMEM, "ensemble tile map: %s", hipGetErrorString(err));
-            }
-            e->dmap2_len = tiles2;
-        }
-        err = hipMemcpy(e->dmap2, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-        if (err != hipSuccess) return hip_fail(err, "ensemble tile map upload");
-    }
+    rc = ens_map(e, tab, tiles2, &e->dmap2, &e->dmap2_len);
+    if (rc) return rc;
     ens_table(e, e->shape.width, (256 / e->shape.width) * e->shape.rpt, tab);
     rc = ens_upload(e, &e->dtab, tab);
+    if (rc) return rc;
+    rc = ens_map(e, tab, tiles, &e->dmap, &e->dmap_len);
     if (rc) return rc;
     e->ntiles = static_cast<int>(tiles);
     kbc::EnsLaunch a{};
@@ -665,6 +674,8 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
     e->dtab2 = nullptr;
     e->dmap2 = nullptr;
     e->dmap2_len = 0;
+    e->dmap = nullptr;
+    e->dmap_len = 0;
     e->blocks = 0;
     // two fused steps per launch where the single lattice uses them
     e->fuse = (m0->p.form == LBM_F16DEV_F32) ? 1 : 2;
@@ -674,6 +685,7 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
         if (e->dtab) (void)hipFree(e->dtab);
         if (e->dtab2) (void)hipFree(e->dtab2);
         if (e->dmap2) (void)hipFree(e->dmap2);
+        if (e->dmap) (void)hipFree(e->dmap);
         delete e;
         return rc;
     }
@@ -728,6 +740,7 @@ int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent) {
     }
     if (singles) {
         a.table = e->dtab;
+        a.tile_member = e->dmap;
         a.ntiles = e->ntiles;
         a.nsteps = singles;
         a.parity = par;
@@ -764,12 +777,13 @@ int lbm_ensemble_get_fusion(const lbm_ens* e, int32_t* rows) {
 int lbm_ensemble_free(lbm_ens* e) {
     if (!e) return LBM_OK;
     int rc = LBM_OK;
-    if (e->dtab || e->dtab2 || e->dmap2) {
+    if (e->dtab || e->dtab2 || e->dmap2 || e->dmap) {
         hipError_t err = hipStreamSynchronize(e->L.stream);
         if (err != hipSuccess) rc = hip_fail(err, "lbm_ensemble_free sync");
         if (e->dtab) (void)hipFree(e->dtab);
         if (e->dtab2) (void)hipFree(e->dtab2);
         if (e->dmap2) (void)hipFree(e->dmap2);
+        if (e->dmap) (void)hipFree(e->dmap);
     }
     delete e;
     return rc;

@@ -3,7 +3,7 @@
 //
 // A device table lists the members (buffers, size, pitch, beta) and the first
 // index of each member's tiles in one global tile numbering (members in order,
-// row-major tiles within a member).  The tile range is cut into eight equal
+// row-major tiles within a member); a per-tile index gives each tile's member.  The tile range is cut into eight equal
 // contiguous bands, one per XCD (workgroup b runs on XCD b % 8), and the
 // workgroups of an XCD deal its band out round-robin, so x-neighbour tiles of
 // one member meet in the same L2 as in the single-lattice step.
@@ -31,8 +31,9 @@ namespace kbc {
 namespace {
 
 template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
-__global__ __launch_bounds__(256) void k_ens(const EnsEntry* __restrict__ tab, int nmem, int ntiles,
-                                             int nsteps, int parity) {
+__global__ __launch_bounds__(256) void k_ens(const EnsEntry* __restrict__ tab,
+                                             const int32_t* __restrict__ tile_member, int ntiles, int nsteps,
+                                             int parity) {
     using F = Form<FORM>;
     using S = typename F::S;
     using R = typename F::R;
@@ -44,13 +45,8 @@ __global__ __launch_bounds__(256) void k_ens(const EnsEntry* __restrict__ tab, i
     for (int s = 0; s < nsteps; ++s) {
         const int par = (parity + s) & 1;
         for (int t = start + j; t < end; t += m) {
-            // member holding tile t: the last entry with tile_start <= t
-            int lo = 0, hi = nmem - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (tab[mid].tile_start <= t) lo = mid; else hi = mid - 1;
-            }
-            const EnsEntry& e = tab[lo];
+            // member holding tile t, from the per-tile index (one scalar load)
+            const EnsEntry& e = tab[tile_member[t]];
             Coef<R> K;
             K.beta = static_cast<R>(e.beta);
             K.inv_beta = static_cast<R>(e.inv_beta);
@@ -140,18 +136,20 @@ struct EnsOp {
             return 0;
         }
         const EnsEntry* tab = a.table;
-        int nmem = a.nmem, ntiles = a.ntiles, nsteps = a.nsteps, parity = a.parity;
+        const int32_t* map = a.tile_member;
+        int ntiles = a.ntiles, nsteps = a.nsteps, parity = a.parity;
+        if (!map) return -1;
         if (!a.persistent) {
             const int band = (ntiles + 7) / 8;
             for (int s = 0; s < nsteps; ++s) {
                 const int one = 1, par = (parity + s) & 1;
-                kern<<<dim3(8u * static_cast<unsigned>(band)), dim3(256), 0, a.stream>>>(tab, nmem, ntiles, one, par);
+                kern<<<dim3(8u * static_cast<unsigned>(band)), dim3(256), 0, a.stream>>>(tab, map, ntiles, one, par);
                 if (hipGetLastError() != hipSuccess) return -2;
             }
             return 0;
         }
         if (a.blocks < 8 || a.blocks % 8) return -1;
-        void* args[] = {&tab, &nmem, &ntiles, &nsteps, &parity};
+        void* args[] = {&tab, &map, &ntiles, &nsteps, &parity};
         if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(static_cast<unsigned>(a.blocks)),
                                        dim3(256), args, 0, a.stream) != hipSuccess)
             return -2;
