@@ -155,7 +155,7 @@ def time_c5(dev):
     return out
 
 
-def time_ensemble(dev, steps=20):
+def time_ensemble(dev, steps=60):
     """The uneven ensemble: 256 members, N in {128, 256, 512, 1024}, KBC-B FP32,
     one batched launch over all members' tiles per step or per two fused
     steps (the library's default)."""
@@ -165,7 +165,7 @@ def time_ensemble(dev, steps=20):
     specs = inputs.ensemble_members(256, master_seed=4)
     sims = make_members(specs, form="f32", device=dev)
     ens = Ensemble(sims)
-    ens.step(2)
+    ens.step(10)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()

@@ -296,8 +296,8 @@ int lbm_ensemble_set_tile(lbm_ens* e, int32_t width, int32_t rows_per_thread, in
 
 /* Steps per launch of lbm_ensemble_step: 1, or 2 (the fused two-step tile of
  * lbm_set_fusion for every member, 64 x `rows` tiles, rows in {8, 16}; 0
- * keeps the current height).  Defaults: 2 steps with 16 rows for FP32, 8
- * rows for FP64, 1 step for FP16.  Bitwise identical either way; the
+ * keeps the current height).  Defaults: 2 steps with 16 rows for FP32 and
+ * FP16, 8 rows for FP64.  Bitwise identical either way; the
  * non-temporal flag of lbm_ensemble_set_tile applies to both.
  * lbm_ensemble_get_fusion returns the steps per launch and stores the rows in
  * *rows when not NULL (-1 for a NULL ensemble).  set_fusion with new rows

@@ -677,8 +677,8 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
     e->dmap = nullptr;
     e->dmap_len = 0;
     e->blocks = 0;
-    // two fused steps per launch where the single lattice uses them
-    e->fuse = (m0->p.form == LBM_F16DEV_F32) ? 1 : 2;
+    // two fused steps per launch, as for single lattices
+    e->fuse = 2;
     e->rows = (m0->p.form == LBM_F64) ? 8 : 16;
     int rc = ens_build(e);
     if (rc) {
