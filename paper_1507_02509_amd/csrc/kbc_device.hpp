@@ -118,6 +118,20 @@ __device__ __forceinline__ void moments_to_pop(R T, R N, R P, R Qx, R Qy, R A, R
     p[8] = q * (am + (Qx - Qy));
 }
 
+// ln(1 + x) for x > -1.  FP32: Goldberg's form (D. Goldberg, "What every
+// computer scientist should know about floating-point arithmetic", 1991,
+// Theorem 4): with u = fl(1 + x), ln(u) x / (u - 1) is accurate to a few
+// units in the last place, because the rounding error of 1 + x cancels
+// between ln(u) and u - 1; ln(u) comes from the hardware base-2 logarithm
+// (about 10 instructions instead of the library's long compensated form).
+// FP64 keeps the library log1p.
+__device__ __forceinline__ float log1pR(float x) {
+    const float u = 1.0f + x;
+    const float d = u - 1.0f;
+    return d == 0.0f ? x : (__builtin_amdgcn_logf(u) * 0.693147180559945309f) * (x * __builtin_amdgcn_rcpf(d));
+}
+__device__ __forceinline__ double log1pR(double x) { return log1p(x); }
+
 // Root of the entropy-maximum condition eq. (result1) in gamma,
 //   F(gamma) = sum_i dh_i ln(1 + x_i) = 0,
 //   x_i = ((1 - beta gamma) dh_i - (2 beta - 1) ds_i) / feq_i,
@@ -130,7 +144,8 @@ __device__ __forceinline__ void moments_to_pop(R T, R N, R P, R Qx, R Qy, R A, R
 // in F takes over, which at a near-equilibrium node lies above the FP32
 // tolerance), or after a fixed number of steps.
 // 1 / feq_i = w_i / rho with w_i = 1 / (W_i (1 + e_i)); ln(1 + x) is taken
-// as log1p(x), exact to rounding for the small x of a near-equilibrium node.
+// as log1pR(x), accurate to rounding for the small x of a near-equilibrium
+// node.
 template <typename R>
 __device__ __forceinline__ R exact_gamma(R gam, const R (&ds)[9], const R (&dh)[9], const R (&w)[9], R ir,
                                          const Coef<R>& K) {
@@ -154,7 +169,7 @@ __device__ __forceinline__ R exact_gamma(R gam, const R (&ds)[9], const R (&dh)[
         R F = R(0), D = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            F = fmaR(dh[i], log1p(x[i]), F);
+            F = fmaR(dh[i], log1pR(x[i]), F);
             D = fmaR(-K.beta * dh[i] * dh[i] * wr[i], rcpR(R(1) + x[i]), D);
         }
         if (!(D < R(0))) break;
