@@ -42,6 +42,7 @@ STEP_SOURCES = [os.path.join(_CSRC, f)
 # of the single-step kernel; the vector peaks are MI355X's published ones
 FLOPS_PER_NODE_STEP = {"f32": 266, "f16": 302, "f64": 382}
 VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f16": 157.3, "f64": 78.6}
+VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s: 256 CUs, 64 lanes, nominal clock
 ADJOINT_SOURCES = [os.path.join(_CSRC, f)
                    for f in ("kbc_adjoint.hip", "kbc_adjoint.hpp", "kbc_tile.hpp", "kbc_device.hpp")]
 
@@ -54,9 +55,9 @@ def kernel_digest(sources=STEP_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key: str, section: str = "step"):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+def measured_traffic(key: str, section: str = "step", field: str = "bytes_per_launch"):
+    """A per-launch figure (HBM bytes by default) from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -67,7 +68,7 @@ def measured_traffic(key: str, section: str = "step"):
     if rec.get("kernel_digest") != kernel_digest(sources):
         return None
     entry = rec.get("workloads", {}).get(key)
-    return None if entry is None else entry.get("bytes_per_launch")
+    return None if entry is None else entry.get(field)
 
 
 def progress(msg: str):
@@ -299,6 +300,14 @@ def main():
                     "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
                     "single_pass_hbm_frac": round(BYTES_PER_NODE[args.form] * nodes / (ms * 1e-3) / 1e9
                                                   / HBM_PEAK_GBS, 4)}
+        # the kernel's own limit: vector instructions issued (counted by the
+        # profiler per node-step) against one instruction per lane and clock
+        # on 256 CUs x 64 lanes at the nominal 2.4 GHz (packed FP32 is not
+        # emitted, so the published FP32 peak above is twice what it can reach)
+        ipn = measured_traffic(key, field="valu_instructions_per_node_step")
+        if ipn:
+            roofline["valu_instructions_per_node_step"] = ipn
+            roofline["valu_issue_frac"] = round(ipn * nodes / (ms * 1e-3) / VALU_ISSUE_PEAK, 4)
     else:
         roofline = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
