@@ -16,7 +16,10 @@
 
 namespace kbc {
 
-// Adjoint of moments_to_pop: moment adjoints from population adjoints pb.
+// Adjoint of the map from a zero-mass, zero-momentum moment vector (T, N, Pi,
+// Q_xyy, Q_yxx, A) to populations, eq. (momentsD2Q9) (the map kbc_forward
+// applies to the 1/4-scaled moments): moment adjoints from population
+// adjoints pb.
 template <typename R>
 __device__ __forceinline__ void pop_to_moments_adj(const R (&pb)[9], R& Tb, R& Nb, R& Pb, R& Qxb,
                                                    R& Qyb, R& Ab) {

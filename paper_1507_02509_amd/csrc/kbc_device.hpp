@@ -33,9 +33,8 @@ enum FormId { F16 = 0, F32 = 1, F64 = 2 };
 // D2Q9 velocities, order (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1)
 constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-// lattice weights 4/9, 1/9, 1/36 and their inverses
+// lattice weights 4/9, 1/9, 1/36
 __host__ __device__ constexpr double weight(int i) { return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
-__host__ __device__ constexpr double inv_weight(int i) { return i == 0 ? 2.25 : (i < 5 ? 9.0 : 36.0); }
 // binary16 storage scale exponents: ~1/W_i rounded to a power of two
 __host__ __device__ constexpr int f16_shift(int i) { return i == 0 ? 1 : (i < 5 ? 3 : 5); }
 
@@ -107,24 +106,6 @@ template <typename R> struct Coef {
     R guard;           // gamma = 2 where <dh|dh> <= guard <ds|ds>
     R gamma_fixed;     // stabiliser for GFIX
 };
-
-// Populations of a zero-mass, zero-momentum moment vector (T, N, Pi, Q_xyy,
-// Q_yxx, A) (density-weighted), eq. (momentsD2Q9).
-template <typename R>
-__device__ __forceinline__ void moments_to_pop(R T, R N, R P, R Qx, R Qy, R A, R (&p)[9]) {
-    const R h = R(0.5), q = R(0.25);
-    const R tp = q * (T + N), tm = q * (T - N);
-    p[0] = A - T;
-    p[1] = tp - h * (Qx + A);
-    p[3] = tp + h * (Qx - A);
-    p[2] = tm - h * (Qy + A);
-    p[4] = tm + h * (Qy - A);
-    const R ap = A + P, am = A - P;
-    p[5] = q * (ap + (Qx + Qy));
-    p[7] = q * (ap - (Qx + Qy));
-    p[6] = q * (am - (Qx - Qy));
-    p[8] = q * (am + (Qx - Qy));
-}
 
 // ln(1 + x) for x > -1.  FP32: Goldberg's form (D. Goldberg, "What every
 // computer scientist should know about floating-point arithmetic", 1991,
