@@ -99,6 +99,32 @@ def test_adjoint_step_parity_f32(orc, coll, var):
     assert acc.item() == pytest.approx(dbo.sum(), rel=1e-3)
 
 
+@pytest.mark.parametrize("coll,var", [("lbgk", "A"), ("kbc", "B")])
+def test_adjoint_step_parity_f16(orc, coll, var):
+    """The adjoint step of the FP16 storage form (FP32 arithmetic) from the
+    oracle's binary16 rounding of the state, which the form decodes exactly:
+    what separates it from the FP64 oracle adjoint at that state is FP32
+    arithmetic alone, so the FP32 bars apply."""
+    nx, ny = 67, 45
+    say("adjoint step f16", coll, var)
+    beta = beta_from_nu(1e-3)
+    f0 = random_state(orc, nx, ny, beta, seed=46, eps=1e-3)
+    lam_next = np.random.default_rng(47).standard_normal((9, ny, nx)).astype(np.float32).astype(np.float64)
+    s = Sim(nx, ny, beta, collision=coll, variant=var, form="f16")
+    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    f0r = orc.round_storage(orc.Params(nx, ny, beta), f0, "f16")
+    s.set_populations(f0)
+    assert np.abs(s.get_populations().cpu().numpy() - f0r).max() < 1e-15
+    lout = s.new_adjoint()
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.adjoint_step(s.state_buffer(), to_lam(s, lam_next), lout, acc)
+    lo, dbo = orc.adjoint_step(oparams(orc, nx, ny, beta, coll, var), f0r, lam_next)
+    err = field_err(s.planes(lout).cpu().numpy(), lo)
+    say("  f16 lam err", err, "dbeta", acc.item(), dbo.sum())
+    assert err < 1e-3
+    assert acc.item() == pytest.approx(dbo.sum(), rel=1e-3)
+
+
 @pytest.mark.parametrize("mode", ["eq", "grad_cd"])
 def test_adjoint_init_parity(orc, mode):
     nx, ny = 67, 45
