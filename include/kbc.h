@@ -58,7 +58,9 @@ enum {
     LBM_EINVAL = -1,        /* invalid argument */
     LBM_EHIP = -2,          /* a HIP runtime call failed */
     LBM_ENOMEM = -3,        /* device or host allocation failed */
-    LBM_ENONFINITE = -4,    /* reserved for callers that check diagnostics */
+    LBM_ENONFINITE = -4,    /* not returned by the library: the code of a non-finite state
+                               that a caller finds with lbm_diagnostics (the Python
+                               binding's checked run raises it) */
     LBM_EUNSUPPORTED = -5   /* valid but not implemented combination */
 };
 

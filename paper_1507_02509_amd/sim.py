@@ -123,6 +123,21 @@ class Sim:
         L.check(self.lib.lbm_step(self.ctx, int(n)), "lbm_step")
         return self
 
+    def step_checked(self, n: int, every: int = 100) -> "Sim":
+        """n steps, reading the diagnostics every `every` steps and at the end;
+        raises NonFiniteState (code LBM_ENONFINITE) at the first check that
+        finds a non-finite density or velocity.  The step kernels themselves
+        never check values."""
+        done = 0
+        while done < n:
+            k = min(every, n - done)
+            self.step(k)
+            done += k
+            d = self.diagnostics()
+            if d["n_nonfinite"]:
+                raise NonFiniteState(self.steps, int(d["n_nonfinite"]))
+        return self
+
     @property
     def steps(self) -> int:
         return int(self.lib.lbm_step_count(self.ctx))
@@ -234,6 +249,15 @@ class Sim:
                 L._lib.lbm_free(self.ctx)
         except Exception:
             pass
+
+
+class NonFiniteState(RuntimeError):
+    """A checked run found non-finite values (LBM_ENONFINITE)."""
+    code = L.LBM_ENONFINITE
+
+    def __init__(self, step: int, count: int):
+        super().__init__(f"non-finite state at step {step}: {count} nodes")
+        self.step, self.count = step, count
 
 
 def copy_probe(dst: torch.Tensor, src: torch.Tensor):

@@ -529,3 +529,33 @@ def test_edge_parameters_f64(orc, case):
         lb.set_populations(f0)
         lb.step(nsteps)
         assert pop_err(fg, lb.get_populations().cpu().numpy()) < 1e-12
+
+
+def test_failure_detection_underresolved_lbgk(orc):
+    """The oracle's instability case (LBGK at nu = 1e-6 on 64^2, seeded field,
+    400 steps; KBC stays finite): the GPU's diagnostics flag the LBGK state as
+    the oracle's do, and a checked run raises NonFiniteState (LBM_ENONFINITE),
+    while KBC-B and KBC-A run the same 400 steps without a flag."""
+    from paper_1507_02509_amd.sim import NonFiniteState
+    n = 64
+    ux, uy = inputs.spectral(n, 8, 0.05, seed=11)
+    beta = beta_from_nu(1e-6)
+    p = orc_params(orc, n, n, beta, "lbgk", "A")
+    do = orc.diagnostics(p, orc.run(p, orc.init(p, ux, uy), 400))
+    bad_oracle = do["n_nonfinite"] > 0 or do["n_feq_nonpos"] > 0 or do["E"] > 1.0
+    assert bad_oracle
+    for form in ("f64", "f32"):
+        s = Sim(n, n, beta, collision="lbgk", form=form).init(ux, uy)
+        s.step(400)
+        d = s.diagnostics()
+        say(f"  lbgk {form}: nonfinite {d['n_nonfinite']} feq<=0 {d['n_feq_nonpos']} E {d['E']:.3e}")
+        assert d["n_nonfinite"] > 0 or d["n_feq_nonpos"] > 0 or d["E"] > 1.0
+        with pytest.raises(NonFiniteState) as ei:
+            Sim(n, n, beta, collision="lbgk", form=form).init(ux, uy).step_checked(2000, every=50)
+        say(f"  checked run raised at step {ei.value.step}")
+    for var in ("B", "A"):
+        s = Sim(n, n, beta, collision="kbc", variant=var, form="f32").init(ux, uy)
+        s.step_checked(400, every=100)
+        d = s.diagnostics()
+        assert d["n_nonfinite"] == 0 and d["n_feq_nonpos"] == 0
+        assert d["E"] < 0.5 * 0.05 ** 2 * 1.01
