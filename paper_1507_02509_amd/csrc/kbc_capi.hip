@@ -23,7 +23,7 @@ struct lbm_ctx {
     int64_t steps;
     kbc::StepShape shape;
     int fuse;               // time steps per launch of lbm_step: 1 or 2
-    int fuse_rows;          // output tile height of the fused launch: 8, 12 or 16
+    int fuse_rows;          // output tile height of the fused launch: 8, 16, 24 or 32
     double* dscratch;       // ux, uy, omega fields + diagnostics partials
     size_t dscratch_elems;
     double* ascratch;       // adjoint: block partials + initial-state stencil fields
