@@ -31,6 +31,10 @@ struct lbm_ctx {
     double* sscratch;       // spectra: velocity fields and their transforms
     size_t sscratch_elems;
     void* fft_plan;         // spectra: cached FFT plan
+    int graph_chunk;        // lbm_step: steps per graph replay (0: every launch eager)
+    hipStream_t cap_stream; // private stream the graphs are captured on
+    hipGraphExec_t gexec[2];  // captured graph_chunk steps, by the buffer holding the start state
+    int gnext[2];           // buffer holding the state after one replay
 };
 
 namespace {
@@ -170,6 +174,11 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     c->sscratch = nullptr;
     c->sscratch_elems = 0;
     c->fft_plan = nullptr;
+    c->graph_chunk = 0;
+    c->cap_stream = nullptr;
+    c->gexec[0] = c->gexec[1] = nullptr;
+    c->gnext[0] = 0;
+    c->gnext[1] = 1;
     rc = kbc::launch_init(c->L, buf_a, rho, ux, uy, grad, mode);
     if (rc) {
         delete c;
@@ -179,9 +188,13 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     return LBM_OK;
 }
 
-int lbm_step(lbm_ctx* c, int32_t nsteps) {
-    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+}  // extern "C"
+
+namespace {
+
+// The launches of nsteps steps on c->L.stream, with the context's buffer
+// index and step counter advanced as they are enqueued.
+int step_eager(lbm_ctx* c, int32_t nsteps) {
     int32_t s = 0;
     if (c->fuse == 2) {
         for (; s + 2 <= nsteps; s += 2) {
@@ -200,6 +213,93 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
     return LBM_OK;
 }
 
+// Discard the captured graphs (after a change to what the launches do).
+int graph_reset(lbm_ctx* c) {
+    if (!c->gexec[0] && !c->gexec[1]) return LBM_OK;
+    int rc = LBM_OK;
+    hipError_t e = hipStreamSynchronize(c->L.stream);
+    if (e != hipSuccess) rc = hip_fail(e, "graph reset sync");
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        c->gexec[k] = nullptr;
+    }
+    return rc;
+}
+
+// One replay of graph_chunk steps, capturing the graph first if this start
+// buffer has none: the eager launches are recorded on the private stream
+// (nothing runs), the context's bookkeeping is rolled back, and the graph is
+// then launched on the context's stream.
+int step_graph(lbm_ctx* c) {
+    const int k = c->cur;
+    if (!c->gexec[k]) {
+        hipError_t e;
+        if (!c->cap_stream) {
+            e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                c->cap_stream = nullptr;
+                return hip_fail(e, "graph capture stream");
+            }
+        }
+        const hipStream_t user = c->L.stream;
+        const int64_t steps0 = c->steps;
+        e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+        c->L.stream = c->cap_stream;
+        const int rc = step_eager(c, c->graph_chunk);
+        c->L.stream = user;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->cap_stream, &g);
+        c->gnext[k] = c->cur;
+        c->cur = k;
+        c->steps = steps0;
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "graph capture end");
+        e = hipGraphInstantiate(&c->gexec[k], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->gexec[k] = nullptr;
+            return hip_fail(e, "graph instantiate");
+        }
+    }
+    const hipError_t e = hipGraphLaunch(c->gexec[k], c->L.stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    c->cur = c->gnext[k];
+    c->steps += c->graph_chunk;
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_step(lbm_ctx* c, int32_t nsteps) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (c->graph_chunk >= 2) {
+        for (; nsteps >= c->graph_chunk; nsteps -= c->graph_chunk) {
+            const int rc = step_graph(c);
+            if (rc) return rc;
+        }
+    }
+    return step_eager(c, nsteps);
+}
+
+int lbm_set_graph(lbm_ctx* c, int32_t chunk) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (chunk != 0 && (chunk < 2 || chunk > (1 << 20)))
+        return fail(LBM_EINVAL, "graph chunk must be 0 or in [2, 2^20] (got %d)", chunk);
+    if (chunk == c->graph_chunk) return LBM_OK;
+    const int rc = graph_reset(c);
+    c->graph_chunk = chunk;
+    return rc;
+}
+
+int lbm_get_graph(const lbm_ctx* c) { return c ? c->graph_chunk : -1; }
+
 int lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (steps_per_launch != 1 && steps_per_launch != 2)
@@ -208,6 +308,8 @@ int lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows) {
         return fail(LBM_EINVAL, "rows must be 0 (keep), 8, 16, 24 or 32 (got %d)", rows);
     if (rows == 32 && c->p.form == LBM_F64)
         return fail(LBM_EUNSUPPORTED, "a 32-row fused FP64 tile does not fit the LDS of a CU");
+    const int rc = graph_reset(c);
+    if (rc) return rc;
     c->fuse = steps_per_launch;
     if (rows) c->fuse_rows = rows;
     return LBM_OK;
@@ -312,6 +414,8 @@ int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t fla
     s.nt = (flags & LBM_TILE_NONTEMPORAL) ? 1 : 0;
     if ((flags & ~LBM_TILE_NONTEMPORAL) != 0) return fail(LBM_EINVAL, "unknown tile flags %d", flags);
     if (!kbc::valid_shape(s)) return fail(LBM_EINVAL, "tile width must be 64, 128 or 256 and rows per thread 1, 2 or 4");
+    const int rc = graph_reset(c);
+    if (rc) return rc;
     c->shape = s;
     return LBM_OK;
 }
@@ -319,6 +423,10 @@ int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t fla
 int lbm_set_beta(lbm_ctx* c, double beta) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!(beta > 0.0 && beta <= 1.0)) return fail(LBM_EINVAL, "beta must be in (0, 1]");
+    if (beta != c->p.beta) {
+        const int rc = graph_reset(c);
+        if (rc) return rc;
+    }
     c->p.beta = beta;
     c->L.beta = beta;
     return LBM_OK;
@@ -327,9 +435,12 @@ int lbm_set_beta(lbm_ctx* c, double beta) {
 int lbm_free(lbm_ctx* c) {
     if (!c) return LBM_OK;
     int rc = LBM_OK;
-    if (c->dscratch || c->ascratch || c->sscratch || c->fft_plan) {
+    if (c->dscratch || c->ascratch || c->sscratch || c->fft_plan || c->gexec[0] || c->gexec[1] || c->cap_stream) {
         hipError_t e = hipStreamSynchronize(c->L.stream);
         if (e != hipSuccess) rc = hip_fail(e, "lbm_free sync");
+        for (int k = 0; k < 2; ++k)
+            if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->dscratch) (void)hipFree(c->dscratch);
         if (c->ascratch) (void)hipFree(c->ascratch);
         if (c->sscratch) (void)hipFree(c->sscratch);

@@ -40,7 +40,7 @@ class Sim:
     def __init__(self, nx: int, ny: int, beta: float, collision: str = "kbc", variant: str = "B",
                  form: str = "f32", gamma_mode: str = "estimate", gamma_guard: float = 1e-12,
                  gamma_fixed: float = 2.0, rho0: float = 1.0, device="cuda:0", tile: tuple | None = None,
-                 pitch_pad: int = 0, fusion: int | None = None):
+                 pitch_pad: int = 0, fusion: int | None = None, graph: int = 0):
         self.lib = L.load()
         self.device = torch.device(device)
         self.nx, self.ny = int(nx), int(ny)
@@ -70,6 +70,7 @@ class Sim:
         self.ctx = ctypes.c_void_p()
         self._tile = tile
         self._fusion = fusion
+        self._graph = int(graph)
         self._inputs = None
 
     # ------------------------------------------------------------------ setup
@@ -88,7 +89,23 @@ class Sim:
             self.set_tile(*self._tile)
         if self._fusion is not None:
             self.set_fusion(*(self._fusion if isinstance(self._fusion, tuple) else (self._fusion,)))
+        if self._graph:
+            self.set_graph(self._graph)
         return self
+
+    def set_graph(self, chunk: int):
+        """Replay every whole `chunk` steps of step() as one HIP graph launch
+        (captured once per start buffer from the same kernel launches; bitwise
+        identical to launching them one by one); 0 launches every kernel
+        directly.  Pays off on small, launch-bound lattices."""
+        self._graph = int(chunk)
+        if self.ctx:
+            L.check(self.lib.lbm_set_graph(self.ctx, self._graph), "lbm_set_graph")
+
+    @property
+    def graph(self) -> int:
+        """Steps per graph replay (0: none)."""
+        return int(self.lib.lbm_get_graph(self.ctx))
 
     def set_fusion(self, steps_per_launch: int, rows: int = 0):
         """Time steps per kernel launch (1, or 2 = two fused steps) and the
