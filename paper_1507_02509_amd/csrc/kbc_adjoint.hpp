@@ -110,19 +110,21 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
         {
 #pragma clang fp contract(fast)
             // g'_i = g_i - 2 beta ds_i - beta gamma dh_i
+            // d g'_i / d beta = -(2 ds_i + gamma dh_i): mu . dg'/dbeta is
+            // -(2 mu.ds + gamma mu.dh), and mu.dh also gives gamma's adjoint
             R dsb[9], dhb[9];
-            R gamb = R(0), db = R(0);
+            R mdh = R(0), mds = R(0);
             const R tb = R(2) * K.beta, bg = K.beta * gam;
     #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 lam[i] = mu[i];
                 dsb[i] = -tb * mu[i];
                 dhb[i] = -bg * mu[i];
-                gamb = fmaR(mu[i], dh[i], gamb);
-                db = fmaR(mu[i], fmaR(gam, dh[i], R(2) * ds[i]), db);
+                mdh = fmaR(mu[i], dh[i], mdh);
+                mds = fmaR(mu[i], ds[i], mds);
             }
-            gamb = -K.beta * gamb;
-            dbeta = -db;
+            R gamb = -K.beta * mdh;
+            dbeta = -fmaR(gam, mdh, R(2) * mds);
             if constexpr (GM != GFIX && !FROZEN) {
                 if (active) {
                     // gamma = 1/beta - (2 - 1/beta) a / b
