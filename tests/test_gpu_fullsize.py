@@ -196,3 +196,47 @@ def test_fullsize_other_collisions_10_steps_sampled(orc, field, coll, var):
         f"bar {bar:.3e}")
     assert np.isfinite(fg).all()
     assert err < bar
+
+
+def test_fullsize_adjoint_step_sampled(orc, field):
+    """The adjoint step at the full size in the configuration the benchmark
+    times (FP32 KBC-B, gamma differentiated, state f^0 of the turbulence
+    field, a seeded normal adjoint field lambda^(n+1)): lambda^n at 52 sampled
+    nodes against the oracle's adjoint step on a 5 x 5 periodic window around
+    each.  lambda^n(x) needs only f^n(x) and lambda^(n+1) at x + v_i, so the
+    window's centre is exact; the oracle builds f^0 there itself from the
+    velocity patch (central differences) and rounds it to binary32 as stored.
+    Bar 1e-3 relative, as for the FP32 adjoint on small lattices (the
+    derivative of gamma carries 1 / <dh|dh>)."""
+    ux, uy = field
+    beta = beta_from_nu(NU)
+    say("full-size adjoint step")
+    s = Sim(N, N, beta, collision="kbc", variant="B", form="f32").init(ux, uy)
+    la, lb = s.new_adjoint(), s.new_adjoint()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    la.normal_(generator=gen)
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.adjoint_step(s.state_buffer(), la, lb, acc)
+    torch.cuda.synchronize()
+    pin, pout = s.planes(la), s.planes(lb)
+    p5 = orc.Params(5, 5, beta, collision=orc.KBC, variant=orc.VARIANTS["B"])
+    d = np.arange(-2, 3)
+    lg, lo = [], []
+    for x, y in sample_nodes():
+        iy = torch.as_tensor((y + d) % N, device="cuda")[:, None]
+        ix = torch.as_tensor((x + d) % N, device="cuda")[None, :]
+        lam_w = np.ascontiguousarray(pin[:, iy, ix].double().cpu().numpy())
+        pu = np.ascontiguousarray(ux[iy, ix].cpu().numpy())
+        pv = np.ascontiguousarray(uy[iy, ix].cpu().numpy())
+        f_w = orc.round_storage(p5, orc.init(p5, pu, pv), "f32")
+        lam_o, _ = orc.adjoint_step(p5, f_w, lam_w)
+        lo.append(lam_o[:, 2, 2])
+        lg.append(pout[:, y, x].double().cpu().numpy())
+    lg, lo = np.array(lg), np.array(lo)
+    err = np.abs(lg - lo).max() / np.abs(lo).max()
+    say(f"  adjoint samples {len(lo)}, err {err:.3e}, dL/dbeta partial sum {acc.item():.6e}")
+    del s, la, lb
+    torch.cuda.empty_cache()
+    assert np.isfinite(lg).all() and np.isfinite(acc.item())
+    assert err < 1e-3
