@@ -69,8 +69,10 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
     const int lane = static_cast<int>(threadIdx.x & 63u);
     const int w = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));   // wave index
 
-    // ---- step 1, interior columns x0 .. x0 + 63 (wrapped), extended rows;
-    // the next row's loads are issued before the current row collides
+    // ---- step 1, interior columns x0 .. x0 + 63 (wrapped), extended rows
+    // (every fourth for each wave); the next row's loads are issued before
+    // the current row collides, into the other of two register sets (the
+    // loop is unrolled by two rows so that no row is copied between them)
     {
         const int gx = pmod(x0 + lane, nx);
         const uint32_t c0 = static_cast<uint32_t>(gx) * sizeof(S);
@@ -90,13 +92,10 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
             v[7] = ld_at(row_ptr(src, yp, 7, pitch), cp);
             v[8] = ld_at(row_ptr(src, yp, 8, pitch), cm);
         };
-        S nxt[9];
-        load_row(w, nxt);
-        for (int ey = w; ey < EH; ey += 4) {
+        auto row = [&](int ey, const S (&v)[9]) {
             R g[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) g[i] = F::dec(nxt[i], i);
-            if (ey + 4 < EH) load_row(ey + 4, nxt);
+            for (int i = 0; i < 9; ++i) g[i] = F::dec(v[i], i);
             collide<R, COLL, VAR, GM>(g, K);
             // node (lane, ey - 1) -> slot (lane + v_x + 1, ey - 1 + v_y); the row test is uniform
 #pragma unroll
@@ -104,6 +103,26 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
                 const int r = ey - 1 + kCy[i];
                 if (r >= 0 && r < TH) win[i][r][lane + 1 + kCx[i]] = F::enc(g[i], i);
             }
+        };
+        // steady state: both prefetches exist, so the wait before each row
+        // covers only that row's loads (a conditional prefetch makes the
+        // compiler wait for all outstanding loads); the last one or two rows
+        // are peeled off
+        S va[9], vb[9];
+        load_row(w, va);
+        int ey = w;
+        for (; ey + 8 < EH; ey += 8) {
+            load_row(ey + 4, vb);
+            row(ey, va);
+            load_row(ey + 8, va);
+            row(ey + 4, vb);
+        }
+        if (ey + 4 < EH) {
+            load_row(ey + 4, vb);
+            row(ey, va);
+            row(ey + 4, vb);
+        } else if (ey < EH) {
+            row(ey, va);
         }
     }
     // ---- step 1, halo columns x0 - 1 and x0 + 64 (wrapped), every extended
