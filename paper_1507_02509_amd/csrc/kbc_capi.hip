@@ -771,7 +771,6 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
             (c->p.collision == LBM_KBC && c->p.variant != m0->p.variant) || c->p.gamma_mode != m0->p.gamma_mode ||
             c->p.stream != m0->p.stream)
             return fail(LBM_EINVAL, "member %d differs in form, collision, variant, stabiliser or stream", r);
-        if (c->p.gamma_mode == LBM_GAMMA_EXACT) return fail(LBM_EUNSUPPORTED, "exact stabiliser in an ensemble");
         for (int32_t q = 0; q < r; ++q)
             if (members[q] == c) return fail(LBM_EINVAL, "member %d repeats member %d", r, q);
     }

@@ -105,17 +105,13 @@ struct Ens2Op {
     }
     static int run(const Lattice& L, const EnsLaunch& a) {
         (void)L;
-        if constexpr (GM == GEXACT) {
-            return -5;
-        } else {
-            if (!a.tile_member) return -1;
-            switch (a.rows * 2 + (a.shape.nt ? 1 : 0)) {
-                case 8 * 2: return go<8, false>(a);
-                case 8 * 2 + 1: return go<8, true>(a);
-                case 16 * 2: return go<16, false>(a);
-                case 16 * 2 + 1: return go<16, true>(a);
-                default: return -1;
-            }
+        if (!a.tile_member) return -1;
+        switch (a.rows * 2 + (a.shape.nt ? 1 : 0)) {
+            case 8 * 2: return go<8, false>(a);
+            case 8 * 2 + 1: return go<8, true>(a);
+            case 16 * 2: return go<16, false>(a);
+            case 16 * 2 + 1: return go<16, true>(a);
+            default: return -1;
         }
     }
 };
@@ -157,11 +153,7 @@ struct EnsOp {
     }
     static int run(const Lattice& L, const EnsLaunch& a) {
         (void)L;
-        if constexpr (GM == GEXACT) {
-            return -5;   // ensembles use the estimate or a fixed stabiliser
-        } else {
-            return shapes(a);
-        }
+        return shapes(a);
     }
     static int shapes(const EnsLaunch& a) {
         const StepShape& sh = a.shape;

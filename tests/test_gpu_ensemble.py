@@ -154,3 +154,35 @@ def test_autotuner_restores_state_and_caches(tmp_path, monkeypatch):
     ref = build(small_specs(), "f32")
     for a, b in zip(states(sims), states(ref)):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("form", ["f32", "f64"])
+def test_ensemble_exact_stabilizer_equals_individual_steps(form):
+    """The exact stabiliser (Newton on eq. (result1)) inside the ensemble
+    kernels: single and fused launches equal stepping every member alone with
+    the same stabiliser, bit for bit (the same per-node code)."""
+    say("ensemble exact gamma", form)
+
+    def build_exact():
+        sims = []
+        for nx, ny, nu, seed in small_specs():
+            if nx >= 8 and ny >= 8:
+                ux, uy = inputs.spectral(nx, 3, 0.05, seed=seed, ny=ny)
+            else:
+                ux, uy = np.full((ny, nx), 0.01), np.full((ny, nx), -0.02)
+            s = Sim(nx, ny, beta_from_nu(nu), variant="B", form=form, gamma_mode="exact")
+            sims.append(s.init(ux, uy))
+        return sims
+
+    ref = build_exact()
+    for s in ref:
+        s.step(9)
+    want = states(ref)
+    for fusion in ((1, 0), (2, 8), (2, 16)):
+        sims = build_exact()
+        ens = Ensemble(sims)
+        ens.set_fusion(*fusion)
+        ens.step(4).step(5)
+        for a, b in zip(states(sims), want):
+            assert torch.equal(a, b), fusion
+        ens.free()
