@@ -35,6 +35,35 @@ def test_node_jacobian_matches_finite_differences(orc, coll, variant):
         np.testing.assert_allclose(db, dbfd, atol=1e-6 * max(np.abs(db).max(), 1e-12))
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_node_jacobian_exact_stabilizer_matches_finite_differences(orc, variant):
+    """With the exact stabiliser the oracle's Newton iteration runs in complex
+    arithmetic too; once F(gamma) is at rounding level its imaginary part is
+    the implicit derivative -F_theta / F_gamma of the root.  Pinned against
+    central differences of the real collision, whose Newton iteration is
+    solved to 1e-15 relative at every perturbed state."""
+    rng = np.random.default_rng(300 + variant)
+    p = orc.Params(1, 1, 0.93, collision=orc.KBC, variant=variant, gamma_mode=orc.GAMMA_EXACT)
+    pe = orc.Params(1, 1, 0.93, collision=orc.KBC, variant=variant)
+    for _ in range(5):
+        f = random_state(rng)
+        J, db = orc.node_jacobian(p, f)
+        Je, _ = orc.node_jacobian(pe, f)
+        h = 1e-6
+        Jfd = np.zeros((9, 9))
+        for j in range(9):
+            e = np.zeros(9)
+            e[j] = h
+            Jfd[:, j] = (orc.node_collide(p, f + e)[0] - orc.node_collide(p, f - e)[0]) / (2 * h)
+        np.testing.assert_allclose(J, Jfd, atol=1e-6 * np.abs(J).max())
+        # the exact root's derivative is not the estimate's
+        assert np.abs(J - Je).max() > 1e-4 * np.abs(J).max()
+        pb, pm = (orc.Params(1, 1, 0.93 + s * h, collision=orc.KBC, variant=variant, gamma_mode=orc.GAMMA_EXACT)
+                  for s in (1, -1))
+        dbfd = (orc.node_collide(pb, f)[0] - orc.node_collide(pm, f)[0]) / (2 * h)
+        np.testing.assert_allclose(db, dbfd, atol=1e-6 * max(np.abs(db).max(), 1e-12))
+
+
 def velocity_loss_and_seed(orc, p, f, utx, uty):
     """L = 1/2 sum |u - u_t|^2 over nodes and dL/df_i = (u - u_t) . (v_i - u) / rho."""
     rho, ux, uy = orc.moments(p, f)
