@@ -77,8 +77,9 @@ typedef enum { LBM_F16DEV_F32 = 0, LBM_F32DEV_F32 = 1, LBM_F64 = 2 } lbm_form;
  * (0, inf), after a step below 1e-15 (FP64) or 5e-7 (FP32 arithmetic)
  * relative, after a step that is not at most half the previous one (rounding
  * noise reached), or after 100 / 20 steps).  LBM_GAMMA_EXACT runs in the step,
- * moments, diagnostics and the ensemble; the adjoint returns
- * LBM_EUNSUPPORTED for it. */
+ * moments, diagnostics, the ensemble and the adjoint (which differentiates the
+ * root by the implicit function theorem, holding gamma where the iteration
+ * stopped without a root). */
 typedef enum { LBM_GAMMA_ESTIMATE = 0, LBM_GAMMA_FIXED = 1, LBM_GAMMA_EXACT = 2 } lbm_gamma_mode;
 /* initial populations: equilibrium eq. (Eq); Grad's approximation eq. (Grad)
  * with Pi = Pi^eq + Pi^(1) (eqs. Peq, P1AC) and velocity gradients from

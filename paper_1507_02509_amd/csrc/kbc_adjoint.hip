@@ -316,11 +316,7 @@ template <int FORM, int COLL, int VAR, int GM>
 struct AdjStepOp {
     static int run(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
                    double* slice, double* acc, const void* fsrc, void* fdst) {
-        if constexpr (GM == GEXACT) {
-            return -5;   // the adjoint of the exact stabiliser is not built
-        } else {
-            return go(L, state, lin, lout, partials, slice, acc, fsrc, fdst);
-        }
+        return go(L, state, lin, lout, partials, slice, acc, fsrc, fdst);
     }
     template <bool FROZEN>
     static void launch(const Lattice& L, const void* state, const void* lin, void* lout, int ntx, int nty,

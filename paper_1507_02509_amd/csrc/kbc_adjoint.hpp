@@ -6,7 +6,10 @@
 // the node's contribution mu . dg'/dbeta.  The stabiliser gamma(f) of
 // eq. (result21) is by default differentiated with the rest of the collision through
 // <ds|dh>, <dh|dh> and the entropic weights 1/feq; where the denominator guard
-// selects gamma = 2 it is a constant.  The forward quantities of the KBC
+// selects gamma = 2 it is a constant.  The exact stabiliser (the root of
+// eq. (result1), found by Newton's method) is differentiated by the implicit
+// function theorem at the root: for F(gamma; ds, dh, 1/feq, beta) = 0,
+// d gamma = -(dF at fixed gamma) / F'(gamma).  The forward quantities of the KBC
 // collision come from kbc_forward(), the code collide() runs, so both take the
 // same guard decisions on the same values; the chain rule then runs through
 // them in reverse order.
@@ -91,7 +94,7 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
         dbeta = R(-2) * db;
     } else {
         KbcNode<R> n;
-        kbc_forward<R, VAR, GM>(g, K, n);
+        kbc_forward<R, VAR, (GM == GEXACT ? GEST : GM)>(g, K, n);
         const R third = R(1.0 / 3.0), ninth = R(1.0 / 9.0);
         ir = n.ir;
         ux = n.ux;
@@ -101,8 +104,12 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
         const R(&ds)[9] = n.ds;
         const R(&dh)[9] = n.dh;
         const R(&w)[9] = n.w;
-        const R gam = n.gam, ratio = n.ratio, bsum = n.b;
+        const R ratio = n.ratio, bsum = n.b;
         const bool active = n.active;
+        R gam = n.gam;
+        if constexpr (GM == GEXACT) {
+            if (active) gam = exact_gamma<R>(gam, ds, dh, w, ir, K);
+        }
 
         // --------------------------------------------------------- reverse
         // (mul + add pairs below may fuse: nothing else is computed from
@@ -127,13 +134,52 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
             dbeta = -fmaR(gam, mdh, R(2) * mds);
             if constexpr (GM != GFIX && !FROZEN) {
                 if (active) {
+                    R wd[9];                                   // adjoint of d_i
+                    if constexpr (GM == GEXACT) {
+                    // F = sum_i dh_i ln(1 + x_i), x_i = y_i wr_i,
+                    // y_i = (1 - beta gamma) dh_i - (2 beta - 1) ds_i, wr_i = w_i / rho:
+                    // dF/d dh_i = ln(1 + x_i) + (1 - beta gamma) dh_i wr_i / (1 + x_i),
+                    // dF/d ds_i = -(2 beta - 1) dh_i wr_i / (1 + x_i),
+                    // dF/d wr_i = dh_i y_i / (1 + x_i),
+                    // dF/d beta = -sum_i dh_i (gamma dh_i + 2 ds_i) wr_i / (1 + x_i),
+                    // F'(gamma) = -beta sum_i dh_i^2 wr_i / (1 + x_i)
+                    const R om = R(1) - K.beta * gam, tbm1 = R(2) * K.beta - R(1);
+                    R wr[9], y[9], r[9], lg[9];
+                    R D = R(0);
+                    bool ok = true;
+    #pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        wr[i] = w[i] * ir;
+                        y[i] = om * dh[i] - tbm1 * ds[i];
+                        const R x = y[i] * wr[i];
+                        ok = ok && (x > R(-1));
+                        r[i] = rcpR(R(1) + x);
+                        lg[i] = log1pR(x);
+                        D = fmaR(-K.beta * dh[i] * dh[i] * wr[i], r[i], D);
+                    }
+                    // where the iteration stopped short of a root (an argument
+                    // of the logarithm left (0, inf), or F' >= 0) gamma is held
+                    const R imp = (ok && D < R(0)) ? -gamb / D : R(0);   // -gamma_bar / F'
+                    R irb = R(0), fb = R(0);
+    #pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const R t = dh[i] * wr[i] * r[i];
+                        dhb[i] = fmaR(imp, fmaR(om, t, lg[i]), dhb[i]);
+                        dsb[i] = fmaR(imp, -tbm1 * t, dsb[i]);
+                        const R wrb = imp * dh[i] * y[i] * r[i];
+                        irb = fmaR(wrb, w[i], irb);
+                        wd[i] = -(wrb * ir) * w[i] * w[i];
+                        fb = fmaR(t, fmaR(gam, dh[i], R(2) * ds[i]), fb);
+                    }
+                    dbeta = fmaR(-imp, fb, dbeta);
+                    drb -= irb * ir * ir;                      // ir = 1 / (rho0 + dr)
+                    } else {
                     // gamma = 1/beta - (2 - 1/beta) a / b
                     const R ib2 = K.inv_beta * K.inv_beta;
                     dbeta = fmaR(gamb, -(R(1) + ratio) * ib2, dbeta);
                     const R rb = -K.two_m_inv_beta * gamb;     // adjoint of a / b
                     const R ab = rb * rcpR(bsum);              // adjoint of a
                     const R bb = -ab * ratio;                  // adjoint of b = -rb a / b^2
-                    R wd[9];                                   // adjoint of d_i
     #pragma unroll
                     for (int i = 0; i < 9; ++i) {
                         // a = sum ds dh w, b = sum dh dh w (c enters the guard only);
@@ -144,6 +190,7 @@ __device__ __forceinline__ void collide_vjp(const R (&g)[9], const R (&mu)[9], c
                         dsb[i] = fmaR(ab, hw, dsb[i]);
                         dhb[i] = fmaR(t + bh, w[i], dhb[i]);
                         wd[i] = -(hw * t) * w[i];
+                    }
                     }
                     // d_i in u: 4/9 - 2|u|^2/3; 1/9 - |u|^2/6 + u_a^2/2 +- u_a/3 (axes);
                     // 1/36 + |u|^2/12 +- u_x u_y/4 + (c.u)/12 (diagonals)

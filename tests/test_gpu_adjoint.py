@@ -234,7 +234,9 @@ def test_checkpoint_interval_does_not_change_the_gradient():
                                              ("f32", 9, 2, {}), ("f32", 21, 5, {}),
                                              ("f32", 23, 4, {"gamma_grad": "frozen"}),
                                              ("f64", 19, 4, {"collision": "lbgk"}),
-                                             ("f32", 19, 4, {"variant": "D", "gamma_guard": 1e-4})])
+                                             ("f32", 19, 4, {"variant": "D", "gamma_guard": 1e-4}),
+                                             ("f32", 19, 4, {"gamma_mode": "exact"}),
+                                             ("f64", 17, 3, {"gamma_mode": "exact", "variant": "A"})])
 def test_overlapped_backward_is_bitwise_identical(form, nsteps, K, kw):
     """The backward pass whose launches each run one adjoint step and one
     recomputation step of the next segment (two slot sets) returns the
@@ -345,3 +347,66 @@ def test_seed_matches_loss_derivative(orc):
     rho, ux, uy = orc.moments(oparams(orc, nx, ny, beta, "kbc", "B"), f0)
     want = a[None] + (bx[None] * (VEL[:, 0, None, None] - ux[None]) + by[None] * (VEL[:, 1, None, None] - uy[None])) / rho[None]
     assert field_err(s.planes(lam).cpu().numpy(), want) < 1e-13
+
+
+def oparams_exact(orc, nx, ny, beta, var):
+    return orc.Params(nx, ny, beta, collision=orc.KBC, variant=orc.VARIANTS[var], gamma_mode=orc.GAMMA_EXACT)
+
+
+@pytest.mark.parametrize("form,var", [("f64", "A"), ("f64", "B"), ("f64", "C"), ("f64", "D"), ("f32", "B")])
+def test_adjoint_step_parity_exact_stabilizer(orc, form, var):
+    """The adjoint of a step with the exact stabiliser (the root of eq.
+    (result1), differentiated by the implicit function theorem on the GPU)
+    against the oracle's complex-step adjoint through its own Newton
+    iteration.  FP64 bar 1e-10 (both roots are solved to 1e-15 relative; the
+    derivative carries 1 / F'(gamma)); FP32 bar 1e-3 as for the estimate."""
+    nx, ny = 67, 45
+    say("adjoint step exact", form, var)
+    beta = beta_from_nu(1e-3)
+    f0 = random_state(orc, nx, ny, beta, seed=60, eps=2e-3)
+    lam_next = np.random.default_rng(61).standard_normal((9, ny, nx))
+    s = Sim(nx, ny, beta, variant=var, form=form, gamma_mode="exact")
+    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    s.set_populations(f0)
+    if form == "f32":
+        f0 = orc.round_storage(orc.Params(nx, ny, beta), f0, "f32")
+        lam_next = lam_next.astype(np.float32).astype(np.float64)
+    lout = s.new_adjoint()
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.adjoint_step(s.state_buffer(), to_lam(s, lam_next), lout, acc)
+    lo, dbo = orc.adjoint_step(oparams_exact(orc, nx, ny, beta, var), f0, lam_next)
+    lg = s.planes(lout).cpu().numpy()
+    err = field_err(lg, lo)
+    # the exact root's adjoint differs from the estimate's: the test can tell them apart
+    le, _ = orc.adjoint_step(oparams(orc, nx, ny, beta, "kbc", var), f0, lam_next)
+    gap = field_err(le, lo)
+    say(f"  lam err {err:.3e} (estimate's adjoint is {gap:.3e} away), dbeta {acc.item():.9e} {dbo.sum():.9e}")
+    assert gap > 1e-6
+    if form == "f64":
+        assert err < 1e-10
+        assert acc.item() == pytest.approx(dbo.sum(), rel=1e-8, abs=1e-12)
+    else:
+        assert err < 1e-3
+        assert acc.item() == pytest.approx(dbo.sum(), rel=1e-3)
+
+
+def test_rollout_gradient_exact_stabilizer_matches_oracle_f64(orc):
+    """Gradient of a final-time velocity loss through 12 steps with the exact
+    stabiliser (checkpointed rollout, initial state included) against the
+    oracle's discrete adjoint with its complex-step Jacobians."""
+    nx, ny, nsteps = 21, 18, 12
+    say("rollout grad exact vs oracle")
+    beta = beta_from_nu(1e-3)
+    ux0, uy0 = inputs.spectral(nx, 2, 0.05, seed=62, ny=ny)
+    tx, ty = inputs.spectral(nx, 2, 0.03, seed=63, ny=ny)
+    u0x = torch.from_numpy(ux0).cuda().requires_grad_(True)
+    u0y = torch.from_numpy(uy0).cuda().requires_grad_(True)
+    b = torch.tensor(beta, dtype=torch.float64, device="cuda", requires_grad=True)
+    rho, ux, uy = rollout(u0x, u0y, b, nsteps, variant="B", form="f64", gamma_mode="exact", checkpoint_every=5)
+    loss = velocity_loss(ux, uy, torch.from_numpy(tx).cuda(), torch.from_numpy(ty).cuda())
+    loss.backward()
+    ogx, ogy, odb = oracle_gradient(orc, oparams_exact(orc, nx, ny, beta, "B"), ux0, uy0, tx, ty, nsteps)
+    errs = (field_err(u0x.grad.cpu().numpy(), ogx), field_err(u0y.grad.cpu().numpy(), ogy),
+            abs(b.grad.item() - odb) / abs(odb))
+    say("  grad errors", errs)
+    assert max(errs) < 1e-9
