@@ -388,21 +388,6 @@ def test_exact_gamma_fused_and_tiles_bitwise(form):
         assert torch.equal(o, outs[0])
 
 
-def test_exact_gamma_unsupported_paths():
-    """The adjoint and the ensemble refuse the exact stabiliser cleanly."""
-    from paper_1507_02509_amd import _lib as L
-    from paper_1507_02509_amd.ensemble import Ensemble
-    nx = ny = 32
-    s = Sim(nx, ny, beta_from_nu(1e-3), variant="B", form="f32", gamma_mode="exact")
-    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)))
-    lam_a, lam_b = s.new_adjoint().zero_(), s.new_adjoint()
-    with pytest.raises(L.KbcError):
-        s.adjoint_step(s.state_buffer(), lam_a, lam_b)
-    torch.cuda.synchronize()
-    with pytest.raises(L.KbcError):
-        Ensemble([s])
-
-
 # ------------------------------------------------------------ symmetries
 @pytest.mark.parametrize("form", ["f32", "f64", "f16"])
 def test_translation_invariance_bitwise(form):
