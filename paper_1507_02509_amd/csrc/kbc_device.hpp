@@ -45,8 +45,12 @@ template <> struct Form<F16> {
     using S = _Float16;
     using R = float;
     static constexpr int bytes = 2;
+    // v 2^-s as one mixed-precision FMA (binary16 operand, binary32 result;
+    // exact: the scale is a power of two).  The +0 addend keeps the FMA from
+    // being rewritten as a conversion and a multiply; it maps a stored -0 to
+    // +0, which no later sum can tell apart.
     __device__ static __forceinline__ R dec(S v, int i) {
-        return static_cast<float>(v) * (1.0f / static_cast<float>(1 << f16_shift(i)));
+        return __builtin_fmaf(static_cast<float>(v), 1.0f / static_cast<float>(1 << f16_shift(i)), 0.0f);
     }
     __device__ static __forceinline__ S enc(R v, int i) {
         return static_cast<_Float16>(v * static_cast<float>(1 << f16_shift(i)));
