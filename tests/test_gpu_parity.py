@@ -579,3 +579,57 @@ def test_graph_replay_is_bitwise_identical(form, fusion):
     a.step(7)
     b.step(7)
     assert torch.equal(b.planes(b.state_buffer()), a.planes(a.state_buffer()))
+
+
+def test_seeded_configuration_sweep(orc):
+    """A seeded sweep across the configuration space: 30 draws of lattice
+    size (tiny, ragged and tile-sized), viscosity (1e-5 .. 1e-2), collision
+    and variant, storage form, launch fusion (single, two fused steps with 8
+    or 16 rows) and step count (1 .. 7), each against the oracle.  FP64
+    against the plain oracle, bar max(1e-12, 100 x the oracle's own shift
+    under a 1e-15 relative perturbation of the start); FP32 against the
+    oracle with the same storage rounding after every step, bar max(1e-5,
+    10 x how far that rounding moves the FP64 oracle); FP16 against that
+    storage-rounded oracle, bar 2e-3 (a binary16 rounding flipped by FP32
+    arithmetic moves a value by about 5e-4 of its plane's largest deviation;
+    the fixed-configuration bar for up to ten steps).  The FP64 and FP32 bars
+    widen only where a draw is ill-conditioned (the self-sensitivity reading
+    of the error metric)."""
+    rng = np.random.default_rng(2024)
+    worst = {}
+    for k in range(30):
+        nx = int(rng.choice([3, 5, 17, 63, 64, 65, 130]))
+        ny = int(rng.choice([3, 4, 16, 31, 47]))
+        beta = beta_from_nu(float(10 ** rng.uniform(-5, -2)))
+        coll, var = CASES[int(rng.integers(len(CASES)))]
+        form = FORMS[int(rng.integers(3))]
+        fusion = [(1, 0), (2, 8), (2, 16)][int(rng.integers(3))]
+        nsteps = int(rng.integers(1, 8))
+        if nx >= 8 and ny >= 8:
+            f0 = random_state(orc, nx, ny, beta, seed=1000 + k)
+        else:
+            p0 = orc_params(orc, nx, ny, beta, "kbc", "B")
+            f0 = orc.init(p0, np.full((ny, nx), 0.02), np.full((ny, nx), -0.01))
+            f0 = f0 * (1 + 2e-3 * np.random.default_rng(1000 + k).standard_normal(f0.shape))
+        p = orc_params(orc, nx, ny, beta, coll, var)
+        s = Sim(nx, ny, beta, collision=coll, variant=var, form=form, fusion=fusion)
+        s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+        s.set_populations(f0)
+        s.step(nsteps)
+        fg = s.get_populations().cpu().numpy()
+        fo = orc.run(p, f0, nsteps)
+        if form == "f64":
+            sens = pop_err(orc.run(p, f0 * (1 + 1e-15), nsteps), fo)
+            bar = max(1e-12, 100 * sens)
+            err = pop_err(fg, fo)
+        else:
+            fst = orc.run(p, orc.round_storage(p, f0, form), nsteps, storage=form)
+            sens = pop_err(fst, fo)
+            bar = max(1e-5, 10 * sens) if form == "f32" else 2e-3
+            err = pop_err(fg, fst)
+        say(f"  {k:2d} {nx}x{ny} beta {beta:.6f} {coll} {var} {form} fusion {fusion} steps {nsteps}: "
+            f"err {err:.2e} bar {bar:.2e}")
+        assert np.isfinite(fg).all()
+        assert err < bar, (k, nx, ny, coll, var, form, fusion, nsteps)
+        worst[form] = max(worst.get(form, 0.0), err / bar)
+    say("  worst err / bar by form", worst)
