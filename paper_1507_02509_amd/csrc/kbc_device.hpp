@@ -139,31 +139,70 @@ __device__ __forceinline__ double log1pR(double x) { return log1p(x); }
 // 1 / feq_i = w_i / rho with w_i = 1 / (W_i (1 + e_i)); ln(1 + x) is taken
 // as log1pR(x), accurate to rounding for the small x of a near-equilibrium
 // node.
+//
+// In FP32, while every |x_i| of a node is below 1/32 (near equilibrium),
+// ln(1 + x) is its Taylor polynomial of degree 6 by Horner's rule: six FMAs
+// against the general form's logarithm, reciprocal and guard; the truncation
+// is below 1.4e-10 relative and the FP32 evaluation within 1.2e-7.  The
+// choice is the node's own (all nine of its arguments small), so a node's
+// result does not depend on which nodes share its wave; a wave skips the
+// general form when none of its nodes needs it.  The quantities that do not change
+// with gamma (dh_i / feq_i, (2 beta - 1) ds_i / feq_i, -beta dh_i^2 / feq_i)
+// are formed once, before the iteration.
+__device__ __forceinline__ float log1p_small(float x) {
+    float p = fmaR(x, -1.0f / 6.0f, 0.2f);
+    p = fmaR(x, p, -0.25f);
+    p = fmaR(x, p, 1.0f / 3.0f);
+    p = fmaR(x, p, -0.5f);
+    p = fmaR(x, p, 1.0f);
+    return x * p;
+}
+
 template <typename R>
 __device__ __forceinline__ R exact_gamma(R gam, const R (&ds)[9], const R (&dh)[9], const R (&w)[9], R ir,
                                          const Coef<R>& K) {
     constexpr int kMaxIt = sizeof(R) == 8 ? 100 : 20;
     const R tol = sizeof(R) == 8 ? R(1e-15) : R(5e-7);
     const R tbm1 = R(2) * K.beta - R(1);
-    R wr[9];
+    R hw[9], sw[9], cd[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) wr[i] = w[i] * ir;
+    for (int i = 0; i < 9; ++i) {
+        const R wr = w[i] * ir;
+        hw[i] = dh[i] * wr;
+        sw[i] = tbm1 * ds[i] * wr;
+        cd[i] = -K.beta * dh[i] * hw[i];
+    }
     R prev = R(1e30);   // size of the previous Newton step
     for (int it = 0; it < kMaxIt; ++it) {
         const R om = R(1) - K.beta * gam;
         R x[9];
         bool ok = true;
+        R amax = R(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            x[i] = (om * dh[i] - tbm1 * ds[i]) * wr[i];
+            x[i] = fmaR(om, hw[i], -sw[i]);
             ok = ok && (x[i] > R(-1));
+            amax = fmax(amax, fabs(x[i]));
         }
         if (!ok) break;
         R F = R(0), D = R(0);
+        bool general = true;
+        if constexpr (sizeof(R) == 4) {
+            if (amax < 1.0f / 32.0f) {
+                general = false;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            F = fmaR(dh[i], log1pR(x[i]), F);
-            D = fmaR(-K.beta * dh[i] * dh[i] * wr[i], rcpR(R(1) + x[i]), D);
+                for (int i = 0; i < 9; ++i) {
+                    F = fmaR(dh[i], log1p_small(x[i]), F);
+                    D = fmaR(cd[i], rcpR(1.0f + x[i]), D);
+                }
+            }
+        }
+        if (general) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                F = fmaR(dh[i], log1pR(x[i]), F);
+                D = fmaR(cd[i], rcpR(R(1) + x[i]), D);
+            }
         }
         if (!(D < R(0))) break;
         const R step = divR(F, D);
