@@ -140,10 +140,11 @@ __device__ __forceinline__ double log1pR(double x) { return log1p(x); }
 // as log1pR(x), accurate to rounding for the small x of a near-equilibrium
 // node.
 //
-// In FP32, while every |x_i| of a node is below 1/32 (near equilibrium),
-// ln(1 + x) is its Taylor polynomial of degree 6 by Horner's rule: six FMAs
-// against the general form's logarithm, reciprocal and guard; the truncation
-// is below 1.4e-10 relative and the FP32 evaluation within 1.2e-7.  The
+// While every |x_i| of a node is below 1/32 (FP32) or 1/64 (FP64), i.e. near
+// equilibrium, ln(1 + x) is its Taylor polynomial, of degree 6 or 10, by
+// Horner's rule: six or ten FMAs against the general form's logarithm,
+// reciprocal and guard (FP32) or the library log1p (FP64).  The truncation is
+// below 1.4e-10 and 8e-20 relative, the evaluation within 1.2e-7 and an ulp.  The
 // choice is the node's own (all nine of its arguments small), so a node's
 // result does not depend on which nodes share its wave; a wave skips the
 // general form when none of its nodes needs it.  The quantities that do not change
@@ -157,6 +158,21 @@ __device__ __forceinline__ float log1p_small(float x) {
     p = fmaR(x, p, 1.0f);
     return x * p;
 }
+// FP64: below 1/64 the Taylor polynomial of degree 10 (truncation below
+// 8e-20 relative, evaluation within an ulp) replaces the library log1p
+__device__ __forceinline__ double log1p_small(double x) {
+    double p = fmaR(x, -1.0 / 10.0, 1.0 / 9.0);
+    p = fmaR(x, p, -1.0 / 8.0);
+    p = fmaR(x, p, 1.0 / 7.0);
+    p = fmaR(x, p, -1.0 / 6.0);
+    p = fmaR(x, p, 1.0 / 5.0);
+    p = fmaR(x, p, -1.0 / 4.0);
+    p = fmaR(x, p, 1.0 / 3.0);
+    p = fmaR(x, p, -1.0 / 2.0);
+    p = fmaR(x, p, 1.0);
+    return x * p;
+}
+template <typename R> constexpr R log1p_small_limit() { return sizeof(R) == 8 ? R(1.0 / 64.0) : R(1.0 / 32.0); }
 
 template <typename R>
 __device__ __forceinline__ R exact_gamma(R gam, const R (&ds)[9], const R (&dh)[9], const R (&w)[9], R ir,
@@ -186,15 +202,12 @@ __device__ __forceinline__ R exact_gamma(R gam, const R (&ds)[9], const R (&dh)[
         }
         if (!ok) break;
         R F = R(0), D = R(0);
-        bool general = true;
-        if constexpr (sizeof(R) == 4) {
-            if (amax < 1.0f / 32.0f) {
-                general = false;
+        const bool general = !(amax < log1p_small_limit<R>());
+        if (!general) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    F = fmaR(dh[i], log1p_small(x[i]), F);
-                    D = fmaR(cd[i], rcpR(1.0f + x[i]), D);
-                }
+            for (int i = 0; i < 9; ++i) {
+                F = fmaR(dh[i], log1p_small(x[i]), F);
+                D = fmaR(cd[i], rcpR(R(1) + x[i]), D);
             }
         }
         if (general) {
