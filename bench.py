@@ -275,7 +275,7 @@ def main():
     d0 = sim.diagnostics()
     ms, wall = time_steps(sim, args.steps, args.warmup)
     progress(f"timed {args.steps} steps: {ms:.4f} ms/step")
-    d = sim.diagnostics()
+    d_main = sim.diagnostics()      # the headline run's end state (the extras reuse d)
     del sim
     torch.cuda.empty_cache()
     nodes = n * n
@@ -416,9 +416,9 @@ def main():
         "roofline": roofline,
         "wall_s_timed": round(wall, 3),
         "final_state": {"steps": args.warmup + args.steps,
-                        "mass_drift_rel": (d["mass"] - d0["mass"]) / d0["mass"],
-                        "E": d["E"], "Z": d["Z"], "gamma_mean": d["gamma"],
-                        "n_nonfinite": d["n_nonfinite"]},
+                        "mass_drift_rel": (d_main["mass"] - d0["mass"]) / d0["mass"],
+                        "E": d_main["E"], "Z": d_main["Z"], "gamma_mean": d_main["gamma"],
+                        "n_nonfinite": d_main["n_nonfinite"]},
         "extras": extras,
     }
     if not args.no_cpu_baseline:
