@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_adj_seed(const typename Form<FORM>::S* 
 }
 
 // ----------------------------------------------------------------- adjoint step
-// Grid: one workgroup per tile of 128 x 2 nodes, 8 * rpx * ntx workgroups
+// Grid: one workgroup per tile of 128 x (2 RPT) nodes, 8 * rpx * ntx workgroups
 // (workgroup b runs on XCD b % 8).  XCD x owns the rpx tile rows from x * rpx
 // on; its workgroups, which the hardware dispatches in order, take that band's
 // tiles strip by strip (vertical strips of at most kAdjStrip tiles) and
@@ -87,11 +87,23 @@ __global__ __launch_bounds__(256) void k_adj_seed(const typename Form<FORM>::S* 
 // k_sum_partials adds it up in a fixed order (no device-scope fence per workgroup: on this GPU such a fence writes
 // back the whole L2 of the XCD).
 constexpr int kAdjStrip = 32;
+// Tile height: 128 x 4 with two nodes per thread (rows r and r + 2) for the
+// FP32 and FP16 forms where the lattice has at least kAdjTwoRowTiles such
+// tiles, which halves the per-node share of the tile mapping and the
+// workgroup reduction (measured 2-3 % on 16384^2); 128 x 2 with one node per
+// thread otherwise: smaller lattices are latency-bound and need the
+// workgroups (512^2 rollouts ran 1.5 % slower with two rows), and FP64 would
+// drop to two waves per SIMD (206 VGPRs).
+constexpr int64_t kAdjTwoRowTiles = 8192;
+inline int adj_rows_per_thread(const Lattice& L) {
+    const int64_t tiles4 = static_cast<int64_t>((L.nx + 127) / 128) * ((L.ny + 3) / 4);
+    return (L.form != F64 && tiles4 >= kAdjTwoRowTiles) ? 2 : 1;
+}
 constexpr int kFold = 2048;   // partials per k_fold workgroup
 
 // The adjoint step of workgroup index bidx (the 256 threads of the calling
 // workgroup must all call it: it holds a workgroup barrier).
-template <int FORM, int COLL, int VAR, int GM, bool FROZEN>
+template <int FORM, int COLL, int VAR, int GM, bool FROZEN, int RPT>
 __device__ __forceinline__ void adj_tile(const typename Form<FORM>::S* __restrict__ state,
                                          const typename Form<FORM>::R* __restrict__ lin,
                                          typename Form<FORM>::R* __restrict__ lout, int nx, int ny,
@@ -100,7 +112,7 @@ __device__ __forceinline__ void adj_tile(const typename Form<FORM>::S* __restric
     using F = Form<FORM>;
     using R = typename F::R;
     using S = typename F::S;
-    constexpr int TW = 128, WR = 2;
+    constexpr int TW = 128, WR = 2 * RPT;
     const int xcd = static_cast<int>(bidx & 7u), u = static_cast<int>(bidx >> 3);
     const int rpx = (nty + 7) >> 3;                            // tile rows per XCD
     const int row0 = xcd * rpx;
@@ -120,56 +132,72 @@ __device__ __forceinline__ void adj_tile(const typename Form<FORM>::S* __restric
     }
     row += row0;
     const int x = col * TW + static_cast<int>(threadIdx.x % TW);
-    const int y = row * WR + static_cast<int>(threadIdx.x / TW);
+    // the wave's first row (a wave covers 64 nodes of one row), then, with two
+    // rows per thread, that row + 2
+    const int ya = __builtin_amdgcn_readfirstlane(row * WR + static_cast<int>(threadIdx.x / TW));
+    const int yb = ya + 2;
     double db = 0.0;
-    if (u < ntx * rows && x < nx && y < ny) {
-        // y is uniform across the wave (a wave covers 64 nodes of one row)
-        const int yu = __builtin_amdgcn_readfirstlane(y);
-        const int ym = (yu == 0) ? ny - 1 : yu - 1;
-        const int yp = (yu == ny - 1) ? 0 : yu + 1;
+    if (u < ntx * rows && x < nx && ya < ny) {
         const uint32_t xm = static_cast<uint32_t>((x == 0) ? nx - 1 : x - 1);
         const uint32_t xp = static_cast<uint32_t>((x == nx - 1) ? 0 : x + 1);
         const uint32_t sS = sizeof(S), sR = sizeof(R);
         const uint32_t x0 = static_cast<uint32_t>(x);
-        R g[9], mu[9], lam[9];
-        // f^n_i(x) sits at x - v_i
-        g[0] = F::dec(ld_at(row_ptr(state, yu, 0, pitch), x0 * sS), 0);
-        g[1] = F::dec(ld_at(row_ptr(state, yu, 1, pitch), xm * sS), 1);
-        g[2] = F::dec(ld_at(row_ptr(state, ym, 2, pitch), x0 * sS), 2);
-        g[3] = F::dec(ld_at(row_ptr(state, yu, 3, pitch), xp * sS), 3);
-        g[4] = F::dec(ld_at(row_ptr(state, yp, 4, pitch), x0 * sS), 4);
-        g[5] = F::dec(ld_at(row_ptr(state, ym, 5, pitch), xm * sS), 5);
-        g[6] = F::dec(ld_at(row_ptr(state, ym, 6, pitch), xp * sS), 6);
-        g[7] = F::dec(ld_at(row_ptr(state, yp, 7, pitch), xp * sS), 7);
-        g[8] = F::dec(ld_at(row_ptr(state, yp, 8, pitch), xm * sS), 8);
-        // mu_i(x) = lam^{n+1}_i(x + v_i)
-        mu[0] = ld_at(row_ptr(lin, yu, 0, pitch), x0 * sR);
-        mu[1] = ld_at(row_ptr(lin, yu, 1, pitch), xp * sR);
-        mu[2] = ld_at(row_ptr(lin, yp, 2, pitch), x0 * sR);
-        mu[3] = ld_at(row_ptr(lin, yu, 3, pitch), xm * sR);
-        mu[4] = ld_at(row_ptr(lin, ym, 4, pitch), x0 * sR);
-        mu[5] = ld_at(row_ptr(lin, yp, 5, pitch), xp * sR);
-        mu[6] = ld_at(row_ptr(lin, yp, 6, pitch), xm * sR);
-        mu[7] = ld_at(row_ptr(lin, ym, 7, pitch), xm * sR);
-        mu[8] = ld_at(row_ptr(lin, ym, 8, pitch), xp * sR);
-        R dbn;
-        collide_vjp<R, COLL, VAR, GM, FROZEN>(g, mu, K, lam, dbn);
+        auto load = [&](int yu, R (&g)[9], R (&mu)[9]) {
+            const int ym = (yu == 0) ? ny - 1 : yu - 1;
+            const int yp = (yu == ny - 1) ? 0 : yu + 1;
+            // f^n_i(x) sits at x - v_i
+            g[0] = F::dec(ld_at(row_ptr(state, yu, 0, pitch), x0 * sS), 0);
+            g[1] = F::dec(ld_at(row_ptr(state, yu, 1, pitch), xm * sS), 1);
+            g[2] = F::dec(ld_at(row_ptr(state, ym, 2, pitch), x0 * sS), 2);
+            g[3] = F::dec(ld_at(row_ptr(state, yu, 3, pitch), xp * sS), 3);
+            g[4] = F::dec(ld_at(row_ptr(state, yp, 4, pitch), x0 * sS), 4);
+            g[5] = F::dec(ld_at(row_ptr(state, ym, 5, pitch), xm * sS), 5);
+            g[6] = F::dec(ld_at(row_ptr(state, ym, 6, pitch), xp * sS), 6);
+            g[7] = F::dec(ld_at(row_ptr(state, yp, 7, pitch), xp * sS), 7);
+            g[8] = F::dec(ld_at(row_ptr(state, yp, 8, pitch), xm * sS), 8);
+            // mu_i(x) = lam^{n+1}_i(x + v_i)
+            mu[0] = ld_at(row_ptr(lin, yu, 0, pitch), x0 * sR);
+            mu[1] = ld_at(row_ptr(lin, yu, 1, pitch), xp * sR);
+            mu[2] = ld_at(row_ptr(lin, yp, 2, pitch), x0 * sR);
+            mu[3] = ld_at(row_ptr(lin, yu, 3, pitch), xm * sR);
+            mu[4] = ld_at(row_ptr(lin, ym, 4, pitch), x0 * sR);
+            mu[5] = ld_at(row_ptr(lin, yp, 5, pitch), xp * sR);
+            mu[6] = ld_at(row_ptr(lin, yp, 6, pitch), xm * sR);
+            mu[7] = ld_at(row_ptr(lin, ym, 7, pitch), xm * sR);
+            mu[8] = ld_at(row_ptr(lin, ym, 8, pitch), xp * sR);
+        };
+        auto finish = [&](int yu, const R (&g)[9], const R (&mu)[9]) {
+            R lam[9], dbn;
+            collide_vjp<R, COLL, VAR, GM, FROZEN>(g, mu, K, lam, dbn);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) st_at<false>(row_ptr(lout, yu, i, pitch), x0 * sR, lam[i]);
-        db = static_cast<double>(dbn);
+            for (int i = 0; i < 9; ++i) st_at<false>(row_ptr(lout, yu, i, pitch), x0 * sR, lam[i]);
+            db += static_cast<double>(dbn);
+        };
+        R ga[9], ma[9];
+        if (RPT == 2 && yb < ny) {
+            // both rows: the second row's loads are in flight while the first is differentiated
+            R gb[9], mb[9];
+            load(ya, ga, ma);
+            load(yb, gb, mb);
+            finish(ya, ga, ma);
+            finish(yb, gb, mb);
+        } else {
+            load(ya, ga, ma);
+            finish(ya, ga, ma);
+        }
     }
     const double s = block_sum(db);
     if (threadIdx.x == 0) partials[bidx] = s;
 }
 
-template <int FORM, int COLL, int VAR, int GM, bool FROZEN>
+template <int FORM, int COLL, int VAR, int GM, bool FROZEN, int RPT>
 __global__ __launch_bounds__(256) void k_adj_step(const typename Form<FORM>::S* __restrict__ state,
                                                   const typename Form<FORM>::R* __restrict__ lin,
                                                   typename Form<FORM>::R* __restrict__ lout, int nx,
                                                   int ny, int64_t pitch, int ntx, int nty,
                                                   Coef<typename Form<FORM>::R> K,
                                                   double* __restrict__ partials) {
-    adj_tile<FORM, COLL, VAR, GM, FROZEN>(state, lin, lout, nx, ny, pitch, ntx, nty, K, partials, blockIdx.x);
+    adj_tile<FORM, COLL, VAR, GM, FROZEN, RPT>(state, lin, lout, nx, ny, pitch, ntx, nty, K, partials, blockIdx.x);
 }
 
 // An adjoint step and, in the same grid, one forward step between two other
@@ -180,7 +208,7 @@ __global__ __launch_bounds__(256) void k_adj_step(const typename Form<FORM>::S* 
 // 8, so both parts keep their XCD banding) run the adjoint tile, the others
 // the forward step's 256 x 1 tiles (the per-node code of every tile shape is
 // the same, so the recomputed states are those of any forward step).
-template <int FORM, int COLL, int VAR, int GM, bool FROZEN>
+template <int FORM, int COLL, int VAR, int GM, bool FROZEN, int RPT>
 __global__ __launch_bounds__(256) void k_adj_step_fwd(const typename Form<FORM>::S* __restrict__ state,
                                                       const typename Form<FORM>::R* __restrict__ lin,
                                                       typename Form<FORM>::R* __restrict__ lout, int nx,
@@ -191,7 +219,8 @@ __global__ __launch_bounds__(256) void k_adj_step_fwd(const typename Form<FORM>:
                                                       typename Form<FORM>::S* __restrict__ dst, int ntx_f,
                                                       int ntiles_f, int per_xcd_f) {
     if (blockIdx.x < nadj) {
-        adj_tile<FORM, COLL, VAR, GM, FROZEN>(state, lin, lout, nx, ny, pitch, ntx, nty, K, partials, blockIdx.x);
+        adj_tile<FORM, COLL, VAR, GM, FROZEN, RPT>(state, lin, lout, nx, ny, pitch, ntx, nty, K, partials,
+                                                   blockIdx.x);
         return;
     }
     const int b = static_cast<int>(blockIdx.x - nadj);
@@ -299,7 +328,8 @@ int ok() { return hipGetLastError() == hipSuccess ? 0 : -2; }
 
 // Workgroups of one adjoint step (= per-workgroup partials it writes).
 int64_t adj_blocks(const Lattice& L) {
-    const int64_t ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;
+    const int wr = 2 * adj_rows_per_thread(L);
+    const int64_t ntx = (L.nx + 127) / 128, nty = (L.ny + wr - 1) / wr;
     return 8 * ((nty + 7) / 8) * ntx;
 }
 
@@ -318,14 +348,14 @@ struct AdjStepOp {
                    double* slice, double* acc, const void* fsrc, void* fdst) {
         return go(L, state, lin, lout, partials, slice, acc, fsrc, fdst);
     }
-    template <bool FROZEN>
+    template <bool FROZEN, int RPT>
     static void launch(const Lattice& L, const void* state, const void* lin, void* lout, int ntx, int nty,
                        int64_t nb, double* out, const void* fsrc, void* fdst) {
         using F = Form<FORM>;
         using R = typename F::R;
         using S = typename F::S;
         if (!fsrc) {
-            k_adj_step<FORM, COLL, VAR, GM, FROZEN><<<dim3(static_cast<unsigned>(nb)), dim3(256), 0, L.stream>>>(
+            k_adj_step<FORM, COLL, VAR, GM, FROZEN, RPT><<<dim3(static_cast<unsigned>(nb)), dim3(256), 0, L.stream>>>(
                 static_cast<const S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx, L.ny, L.pitch,
                 ntx, nty, make_coef<R>(L), out);
             return;
@@ -335,14 +365,15 @@ struct AdjStepOp {
         const int ntiles_f = ntx_f * L.ny;
         const int per_xcd_f = (ntiles_f + 7) / 8;
         const int64_t grid = nb + 8 * static_cast<int64_t>(per_xcd_f);
-        k_adj_step_fwd<FORM, COLL, VAR, GM, FROZEN><<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, L.stream>>>(
+        k_adj_step_fwd<FORM, COLL, VAR, GM, FROZEN, RPT><<<dim3(static_cast<unsigned>(grid)), dim3(256), 0, L.stream>>>(
             static_cast<const S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx, L.ny, L.pitch,
             ntx, nty, make_coef<R>(L), out, static_cast<unsigned>(nb), static_cast<const S*>(fsrc),
             static_cast<S*>(fdst), ntx_f, ntiles_f, per_xcd_f);
     }
     static int go(const Lattice& L, const void* state, const void* lin, void* lout, double* partials,
                   double* slice, double* acc, const void* fsrc, void* fdst) {
-        const int ntx = (L.nx + 127) / 128, nty = (L.ny + 1) / 2;
+        const int rpt = adj_rows_per_thread(L);
+        const int ntx = (L.nx + 127) / 128, nty = (L.ny + 2 * rpt - 1) / (2 * rpt);
         const int64_t nb = adj_blocks(L);
         if (static_cast<int64_t>(ntx) * nty > (int64_t{1} << 30) || nb > (int64_t{1} << 31) - 1) return -1;
         if ((fsrc == nullptr) != (fdst == nullptr)) return -1;
@@ -351,10 +382,21 @@ struct AdjStepOp {
         const bool direct = nb <= kDirect;
         if (!slice || (!direct && !partials)) return -1;
         double* out = direct ? slice : partials;
-        if (L.adj_frozen)
-            launch<true>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
-        else
-            launch<false>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
+        if constexpr (FORM == F64) {
+            if (rpt != 1) return -1;
+            if (L.adj_frozen)
+                launch<true, 1>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
+            else
+                launch<false, 1>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
+        } else {
+            if (L.adj_frozen) {
+                if (rpt == 2) launch<true, 2>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
+                else launch<true, 1>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
+            } else {
+                if (rpt == 2) launch<false, 2>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
+                else launch<false, 1>(L, state, lin, lout, ntx, nty, nb, out, fsrc, fdst);
+            }
+        }
         if (ok()) return -2;
         const int64_t len = adj_slice_len(L);
         if (!direct) {

@@ -410,3 +410,45 @@ def test_rollout_gradient_exact_stabilizer_matches_oracle_f64(orc):
             abs(b.grad.item() - odb) / abs(odb))
     say("  grad errors", errs)
     assert max(errs) < 1e-9
+
+
+def test_adjoint_two_rows_per_thread_f32(orc):
+    """FP32 lattices with at least 8192 tiles of 128 x 4 run the adjoint with
+    two nodes per thread (rows r and r + 2).  On a ragged 1030 x 3650 lattice
+    (the last tile column 6 nodes wide, the last tile row 2 rows high) the
+    adjoint step matches the oracle's to the FP32 bar of the small lattices,
+    and the overlapped backward pass equals the plain one bit for bit."""
+    nx, ny = 1030, 3650
+    say("adjoint two rows per thread", nx, ny)
+    beta = beta_from_nu(1e-3)
+    f0 = random_state(orc, nx, ny, beta, seed=64, eps=1e-3)
+    lam_next = np.random.default_rng(65).standard_normal((9, ny, nx)).astype(np.float32).astype(np.float64)
+    s = Sim(nx, ny, beta, variant="B", form="f32")
+    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    s.set_populations(f0)
+    f0r = orc.round_storage(orc.Params(nx, ny, beta), f0, "f32")
+    lout = s.new_adjoint()
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.adjoint_step(s.state_buffer(), to_lam(s, lam_next), lout, acc)
+    lg = s.planes(lout).cpu().numpy()
+    del s, lout
+    torch.cuda.empty_cache()
+    p = oparams(orc, nx, ny, beta, "kbc", "B")
+    p.threads = 16
+    lo, dbo = orc.adjoint_step(p, f0r, lam_next)
+    err = field_err(lg, lo)
+    say(f"  lam err {err:.3e}, dbeta {acc.item():.9e} {dbo.sum():.9e}")
+    assert err < 1e-3
+    assert acc.item() == pytest.approx(dbo.sum(), rel=1e-3)
+    ux0, uy0 = inputs.spectral(nx, 3, 0.05, seed=66, ny=ny)
+    grads = []
+    for overlap in (False, True):
+        u0x = torch.from_numpy(ux0).cuda().requires_grad_(True)
+        u0y = torch.from_numpy(uy0).cuda().requires_grad_(True)
+        b = torch.tensor(beta, dtype=torch.float64, device="cuda", requires_grad=True)
+        _, ux, uy = rollout(u0x, u0y, b, 9, form="f32", checkpoint_every=3, overlap=overlap)
+        (0.5 * (ux ** 2 + uy ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        grads.append((u0x.grad.clone(), u0y.grad.clone(), b.grad.clone()))
+    for a, c in zip(grads[1], grads[0]):
+        assert torch.equal(a, c)
