@@ -24,6 +24,7 @@ import torch
 
 from paper_1507_02509_amd import inputs
 from paper_1507_02509_amd.sim import Sim, beta_from_nu
+from oracle_sensitivity import K_SENS, SEEDS, perturbed
 
 pytestmark = pytest.mark.gpu
 
@@ -101,7 +102,7 @@ def test_fullsize_one_step_sampled(orc, field, form):
     assert err < TOL[form]
 
 
-def oracle_window(orc, ux, uy, beta, x, y, nsteps, collision="kbc", variant="B", storage=None, perturb=0.0):
+def oracle_window(orc, ux, uy, beta, x, y, nsteps, collision="kbc", variant="B", storage=None, perturb_seed=None):
     """f^nsteps at (x, y) from the oracle run on a periodic window of half-width
     nsteps + 2 cut from the full field around (x, y).  After n steps a node
     depends on the initial velocity within distance n + 1 (n streaming steps
@@ -116,7 +117,9 @@ def oracle_window(orc, ux, uy, beta, x, y, nsteps, collision="kbc", variant="B",
     pv = np.ascontiguousarray(uy[iy, ix].cpu().numpy())
     p = orc.Params(2 * h + 1, 2 * h + 1, beta, collision=orc.LBGK if collision == "lbgk" else orc.KBC,
                    variant=orc.VARIANTS[variant], threads=4)
-    f0 = orc.init(p, pu, pv) * (1 + perturb)
+    f0 = orc.init(p, pu, pv)
+    if perturb_seed is not None:
+        f0 = perturbed(f0, perturb_seed)
     if storage is not None:
         f0 = orc.round_storage(p, f0, storage)
     f = orc.run(p, f0, nsteps, storage=storage)
@@ -164,10 +167,10 @@ def test_fullsize_other_collisions_10_steps_sampled(orc, field, coll, var, form)
     default launch configuration (two fused steps per launch): after 10
     steps, against the oracle on windows around 12 sampled nodes.
 
-    Bar: max(MULTI_TOL, k s), s = how far the form's own rounding alone moves
+    Bar: max(MULTI_TOL, 5 s), s = how far the form's own rounding alone moves
     the oracle (FP32 / FP16: the oracle re-run with every stored state rounded
-    to the form, k = 10; FP64: a 1e-15 relative perturbation of the start,
-    k = 100), measured from the oracle alone, no GPU value.  Variants C and D
+    to the form; FP64: 1e-15 relative perturbations of the start, the largest
+    of three seeds), measured from the oracle alone, no GPU value.  Variants C and D
     leave only third- and fourth-order moments in dh, so <dh|dh> is tiny and
     gamma's ratio amplifies rounding: in FP32, s is about 6e-5 for them on
     this field against 5e-8 for B and LBGK and 4e-6 for A, and the GPU, which
@@ -190,16 +193,15 @@ def test_fullsize_other_collisions_10_steps_sampled(orc, field, coll, var, form)
     fo = np.array([oracle_window(orc, ux, uy, beta, x, y, 10, coll, var) for x, y in pts])
     scale = np.abs(fo - W).max()
     if form == "f64":
-        fs = np.array([oracle_window(orc, ux, uy, beta, x, y, 10, coll, var, perturb=1e-15) for x, y in pts])
-        k = 100
+        sens = max(np.abs(np.array([oracle_window(orc, ux, uy, beta, x, y, 10, coll, var, perturb_seed=sd)
+                                    for x, y in pts]) - fo).max() for sd in SEEDS) / scale
     else:
         fs = np.array([oracle_window(orc, ux, uy, beta, x, y, 10, coll, var, storage=form) for x, y in pts])
-        k = 10
-    sens = np.abs(fs - fo).max() / scale
-    bar = max(MULTI_TOL[form], k * sens)
+        sens = np.abs(fs - fo).max() / scale
+    bar = max(MULTI_TOL[form], K_SENS * sens)
     err = np.abs(fg - fo).max() / scale
     say(f"  {coll} {var} {form} after 10 steps: samples {len(pts)}, err {err:.3e}, sensitivity {sens:.3e}, "
-        f"bar {bar:.3e}")
+        f"bar {bar:.3e}, err/bar {err / bar:.3f}")
     assert np.isfinite(fg).all()
     assert err < bar
 
@@ -212,7 +214,7 @@ def test_fullsize_adjoint_step_sampled(orc, field):
     each.  lambda^n(x) needs only f^n(x) and lambda^(n+1) at x + v_i, so the
     window's centre is exact; the oracle builds f^0 there itself from the
     velocity patch (central differences) and rounds it to binary32 as stored.
-    Bar 1e-3 relative, as for the FP32 adjoint on small lattices (the
+    Bar 1e-4 relative, as for the FP32 adjoint on small lattices (the
     derivative of gamma carries 1 / <dh|dh>)."""
     ux, uy = field
     beta = beta_from_nu(NU)
@@ -245,4 +247,4 @@ def test_fullsize_adjoint_step_sampled(orc, field):
     del s, la, lb
     torch.cuda.empty_cache()
     assert np.isfinite(lg).all() and np.isfinite(acc.item())
-    assert err < 1e-3
+    assert err < 1e-4

@@ -18,6 +18,7 @@ import torch
 
 from paper_1507_02509_amd import inputs
 from paper_1507_02509_amd.sim import Sim, beta_from_nu
+from oracle_sensitivity import K_SENS, self_sensitivity
 
 pytestmark = pytest.mark.gpu
 
@@ -135,37 +136,49 @@ def field_err(a, b):
 def test_tgv_64_fp64_1000_steps(orc, coll, var, k):
     """The small Green-Taylor workload: 64^2, u0 = 0.04, nu = 0.01, FP64, 1000
     steps, Grad initialisation with central differences.  Fields (each
-    population plane, rho, u_x, u_y) agree to 1e-12 relative -- except where
-    the method itself is ill-conditioned: models A and C on the (1, 4) vortex
-    amplify a 1e-15 perturbation of the oracle's own initial state to ~1e-5 in
-    u (gamma* projects ds onto a nearly vanishing dh), so there the bar is the
-    oracle's measured self-sensitivity."""
-    n, nu, steps = 64, 0.01, 1000
+    population plane, rho, u_x, u_y) agree to 1e-12 relative after 100 and
+    after 1000 steps -- except where the method itself is ill-conditioned:
+    models A and C on the (1, 4) vortex, where <dh|dh> passes near zero at
+    some nodes while <ds|dh> does not (the mechanism is shown on the CPU in
+    test_oracle_lattice.py).  There the oracle moves by 1e-10 (100 steps) to
+    1e-5 (1000 steps) under a 1e-15 perturbation of its own start, and the
+    bar is 5 times that self-sensitivity (the largest over three seeded
+    perturbations), measured from the oracle alone."""
+    n, nu = 64, 0.01
     say("tgv 64 fp64", coll, var, k)
     beta = beta_from_nu(nu)
     ux, uy = inputs.tgv(n, 0.04, *k)
     s = Sim(n, n, beta, collision=coll, variant=var, form="f64").init(ux, uy)
-    s.step(steps)
-    fg = s.get_populations().cpu().numpy()
-    rho, vx, vy = (t.cpu().numpy() for t in s.moments())
     p = orc_params(orc, n, n, beta, coll, var)
     f0 = orc.init(p, ux, uy)
-    fo = orc.run(p, f0, steps)
-    orho, ovx, ovy = orc.moments(p, fo)
-    errs = (max(field_err(fg[i], fo[i]) for i in range(9)), field_err(rho, orho),
-            field_err(vx, ovx), field_err(vy, ovy))
-    bar = 1e-12
-    if coll == "kbc" and var in ("A", "C") and k == (1, 4):
-        rng = np.random.default_rng(0)
-        fp = orc.run(p, f0 * (1 + 1e-15 * rng.standard_normal(f0.shape)), steps)
-        _, px, py = orc.moments(p, fp)
-        sens = max(max(field_err(fp[i], fo[i]) for i in range(9)), field_err(px, ovx), field_err(py, ovy))
-        say("  oracle self-sensitivity", sens)
-        bar = max(bar, 100 * sens)
-    say("  tgv errors (pop, rho, ux, uy)", errs, "bar", bar)
-    assert max(errs) < bar
+    ill = coll == "kbc" and var in ("A", "C") and k == (1, 4)
+
+    def fields(f):
+        r, vx, vy = orc.moments(p, f)
+        return f, r, vx, vy
+
+    def errs_of(a, b):
+        return (max(field_err(a[0][i], b[0][i]) for i in range(9)), field_err(a[1], b[1]),
+                field_err(a[2], b[2]), field_err(a[3], b[3]))
+
+    done, fo = 0, f0
+    for steps in (100, 1000):
+        s.step(steps - done)
+        fg = s.get_populations().cpu().numpy()
+        fo = orc.run(p, fo, steps - done)
+        done = steps
+        got, want = fields(fg), fields(fo)
+        errs = errs_of(got, want)
+        bar = 1e-12
+        if ill:
+            sens = self_sensitivity(lambda f: fields(orc.run(p, f, steps)), f0, want, lambda a, b: max(errs_of(a, b)))
+            say(f"  oracle self-sensitivity after {steps} steps", sens)
+            bar = max(bar, K_SENS * sens)
+        say(f"  tgv errors after {steps} steps (pop, rho, ux, uy)", errs, "bar", bar, "err/bar", max(errs) / bar)
+        assert max(errs) < bar
     # and the flow is the vortex: analytic decay within the scheme's O(h^2 + Ma^2)
-    ax, ay = inputs.tgv(n, 0.04, *k, nu=nu, t=steps)
+    vx, vy = got[2], got[3]
+    ax, ay = inputs.tgv(n, 0.04, *k, nu=nu, t=done)
     err = np.sqrt(((vx - ax) ** 2 + (vy - ay) ** 2).sum() / (ax ** 2 + ay ** 2).sum())
     assert err < (5e-3 if k == (1, 1) else 3e-2)
 
@@ -276,6 +289,57 @@ def test_diagnostics_parity(orc, form):
     # gamma is computed in the form's arithmetic
     tol = 1e-9 if form == "f64" else 5e-2
     assert dg["gamma"] == pytest.approx(do["gamma"], rel=tol)
+
+
+# Per-node gamma of the reduced forms against the FP64 oracle's gamma of the
+# same stored state: what differs is the FP32 arithmetic of the collision.
+# gamma* = 1/beta - (2 - 1/beta) <ds|dh> / <dh|dh> takes <dh|dh> from the
+# third- and fourth-order moments of df, which FP32 forms by cancellation
+# between deviations about 1e3 times larger, so its relative error grows as
+# <dh|dh> / <ds|ds> shrinks.  Stated per state and variant: the median and
+# the 99th percentile of |gamma_gpu - gamma_oracle| over all nodes, and its
+# maximum over the nodes with <dh|dh> >= 1e-3 <ds|ds>.  Measured on MI355X
+# over both states, both forms and all variants: median <= 1.1e-6, 99th
+# percentile <= 4.9e-5, that maximum <= 4.6e-4 (over all nodes, where
+# <dh|dh> nearly vanishes, up to 2.2e-3); no guard decision differed.  The
+# bars are about five times those figures.
+GAMMA_BARS = {  # (median, p99, max where <dh|dh> >= 1e-3 <ds|ds>)
+    "turbulence": (5e-6, 2.5e-4, 2.5e-3),
+    "random": (5e-6, 2.5e-4, 2.5e-3),
+}
+
+
+@pytest.mark.parametrize("state", ["turbulence", "random"])
+@pytest.mark.parametrize("var", ["A", "B", "C", "D"])
+@pytest.mark.parametrize("form", ["f32", "f16"])
+def test_gamma_field_parity_reduced_forms(orc, form, var, state):
+    nx, ny = 131, 70
+    beta = beta_from_nu(1e-4)
+    p = orc_params(orc, nx, ny, beta, "kbc", var)
+    if state == "turbulence":
+        ux, uy = inputs.spectral(nx, 5, 0.05, seed=33, ny=ny)
+        f = orc.run(p, orc.init(p, ux, uy), 20)
+    else:
+        f = random_state(orc, nx, ny, beta, seed=34)
+    f = orc.round_storage(p, f, form)
+    s = Sim(nx, ny, beta, variant=var, form=form)
+    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+    s.set_populations(f)
+    gg = s.moments(gamma=True)[3].cpu().numpy()
+    go = orc.gamma_field(p, f)
+    prods = np.array([[orc.node_deviations(orc.VARIANTS[var], f[:, y, x])[2] for x in range(nx)]
+                      for y in range(ny)])
+    ratio = prods[..., 1] / prods[..., 2]          # <dh|dh> / <ds|ds>
+    err = np.abs(gg - go)
+    wc = ratio >= 1e-3
+    med, p99 = float(np.median(err)), float(np.quantile(err, 0.99))
+    mwc = float(err[wc].max()) if wc.any() else 0.0
+    say(f"  gamma {form} {var} {state}: |gamma| median {np.median(np.abs(go)):.3f}; error median {med:.2e}, "
+        f"p99 {p99:.2e}, max {err.max():.2e}; nodes with <dh|dh> >= 1e-3 <ds|ds>: {wc.mean():.3f}, "
+        f"their max error {mwc:.2e}; guard decisions differing: {int(((gg == 2) != (go == 2)).sum())}")
+    bm, bp, bw = GAMMA_BARS[state]
+    assert np.isfinite(gg).all()
+    assert med < bm and p99 < bp and mwc < bw
 
 
 def test_mass_momentum_conservation_f64():
@@ -586,10 +650,10 @@ def test_seeded_configuration_sweep(orc):
     size (tiny, ragged and tile-sized), viscosity (1e-5 .. 1e-2), collision
     and variant, storage form, launch fusion (single, two fused steps with 8
     or 16 rows) and step count (1 .. 7), each against the oracle.  FP64
-    against the plain oracle, bar max(1e-12, 100 x the oracle's own shift
-    under a 1e-15 relative perturbation of the start); FP32 against the
-    oracle with the same storage rounding after every step, bar max(1e-5,
-    10 x how far that rounding moves the FP64 oracle); FP16 against that
+    against the plain oracle, bar max(1e-12, 5 x the oracle's own shift
+    under 1e-15 relative perturbations of the start, largest of three seeds);
+    FP32 against the oracle with the same storage rounding after every step,
+    bar max(1e-5, 5 x how far that rounding moves the FP64 oracle); FP16 against that
     storage-rounded oracle, bar 2e-3 (a binary16 rounding flipped by FP32
     arithmetic moves a value by about 5e-4 of its plane's largest deviation;
     the fixed-configuration bar for up to ten steps).  The FP64 and FP32 bars
@@ -619,13 +683,13 @@ def test_seeded_configuration_sweep(orc):
         fg = s.get_populations().cpu().numpy()
         fo = orc.run(p, f0, nsteps)
         if form == "f64":
-            sens = pop_err(orc.run(p, f0 * (1 + 1e-15), nsteps), fo)
-            bar = max(1e-12, 100 * sens)
+            sens = self_sensitivity(lambda f: orc.run(p, f, nsteps), f0, fo, pop_err)
+            bar = max(1e-12, K_SENS * sens)
             err = pop_err(fg, fo)
         else:
             fst = orc.run(p, orc.round_storage(p, f0, form), nsteps, storage=form)
             sens = pop_err(fst, fo)
-            bar = max(1e-5, 10 * sens) if form == "f32" else 2e-3
+            bar = max(1e-5, K_SENS * sens) if form == "f32" else 2e-3
             err = pop_err(fg, fst)
         say(f"  {k:2d} {nx}x{ny} beta {beta:.6f} {coll} {var} {form} fusion {fusion} steps {nsteps}: "
             f"err {err:.2e} bar {bar:.2e}")

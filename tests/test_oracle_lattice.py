@@ -261,3 +261,81 @@ def test_table_2dturbsetup_enstrophy_ratio(orc):
     for c in cols:
         assert c["Z0"] ** -0.5 == pytest.approx(c["te"], rel=2e-3)
         assert c["N"] * np.sqrt(2 * c["E0"]) / c["nu"] == pytest.approx(c["Re"], rel=1e-2)
+
+
+def test_kbc_a_c_ill_conditioning_mechanism(orc):
+    """Why FP64 parity of models A and C on the (1, 4) Green-Taylor vortex is
+    held to the oracle's own sensitivity (tests/oracle_sensitivity.py) and B
+    and D are not.  A and C keep the trace T in the shear part, so <ds|dh>
+    has a zeroth-order term (eq. (dsdh0B)) and stays finite where <dh|dh>
+    passes near zero; there gamma* = 1/beta - (2 - 1/beta) <ds|dh>/<dh|dh> is
+    nearly singular.  Runs of the oracle from its initial state and from the
+    same state perturbed by 1e-15 (relative, seed 0):
+      * B and D stay within 1e-10 of each other (deviation-relative) for 300 steps;
+      * C: the step at which they part fastest is a passage of some node's
+        <dh|dh> / <ds|ds> below 1e-5 with |gamma| > 10 in both runs, and no
+        node is on different sides of the guard there;
+      * A: at one step a node's <dh|dh> / <ds|ds> falls on opposite sides of
+        the guard eps_g = 1e-12 in the two runs, gamma switches between 2
+        and a value of magnitude above 100 at that node, and the runs' distance
+        jumps by more than 100x in that one step."""
+    from oracle_sensitivity import perturbed
+    n, nu = 64, 0.01
+    beta = orc.beta_from_nu(nu)
+    ux, uy = inputs.tgv(n, 0.04, 1, 4)
+    W = orc.weights()[:, None, None]
+
+    def dist(a, b):
+        return float(np.abs(a - b).max() / np.abs(b - W).max())
+
+    def ratio(var, f, y, x):
+        _, _, (_, b, c) = orc.node_deviations(var, f[:, y, x])
+        return b / c
+
+    for var in (orc.KBC_B, orc.KBC_D):
+        p = orc.Params(n, n, beta, collision=orc.KBC, variant=var)
+        f0 = orc.init(p, ux, uy)
+        assert dist(orc.run(p, perturbed(f0, 0), 300), orc.run(p, f0, 300)) < 1e-10
+
+    # model C: steps 280 .. 299
+    var = orc.KBC_C
+    p = orc.Params(n, n, beta, collision=orc.KBC, variant=var)
+    f0 = orc.init(p, ux, uy)
+    fa, fb = orc.run(p, f0, 280), orc.run(p, perturbed(f0, 0), 280)
+    best = (0.0, None)
+    for t in range(280, 300):
+        ga, gb = orc.gamma_field(p, fa), orc.gamma_field(p, fb)
+        assert np.array_equal(ga == 2.0, gb == 2.0)          # no guard crossing
+        d0 = dist(fb, fa)
+        na, nb = orc.step(p, fa), orc.step(p, fb)
+        grow = dist(nb, na) / d0
+        if grow > best[0]:
+            best = (grow, t, fa, fb, ga, gb)
+        fa, fb = na, nb
+    grow, t, fa, fb, ga, gb = best
+    assert grow > 5.0
+    big = np.argwhere((np.abs(ga) > 10) & (np.abs(gb) > 10))
+    assert len(big)
+    assert min(max(ratio(var, fa, y, x), ratio(var, fb, y, x)) for y, x in big) < 1e-5
+    assert dist(fb, fa) > 1e4 * 1e-10
+
+    # model A: steps 460 .. 469
+    var = orc.KBC_A
+    p = orc.Params(n, n, beta, collision=orc.KBC, variant=var)
+    f0 = orc.init(p, ux, uy)
+    fa, fb = orc.run(p, f0, 460), orc.run(p, perturbed(f0, 0), 460)
+    crossed = False
+    for t in range(460, 470):
+        ga, gb = orc.gamma_field(p, fa), orc.gamma_field(p, fb)
+        flips = np.argwhere((ga == 2.0) != (gb == 2.0))
+        d0 = dist(fb, fa)
+        na, nb = orc.step(p, fa), orc.step(p, fb)
+        if len(flips):
+            y, x = flips[0]
+            ra, rb = ratio(var, fa, y, x), ratio(var, fb, y, x)
+            assert min(ra, rb) <= p.gamma_guard < max(ra, rb)
+            assert max(abs(ga[y, x]), abs(gb[y, x])) > 100
+            assert dist(nb, na) > 100 * d0
+            crossed = True
+        fa, fb = na, nb
+    assert crossed
