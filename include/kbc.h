@@ -61,7 +61,9 @@ enum {
     LBM_ENONFINITE = -4,    /* not returned by the library: the code of a non-finite state
                                that a caller finds with lbm_diagnostics (the Python
                                binding's checked run raises it) */
-    LBM_EUNSUPPORTED = -5   /* valid but not implemented combination */
+    LBM_EUNSUPPORTED = -5,  /* valid but not implemented combination */
+    LBM_ESYNC = -6          /* a persistent ensemble launch gave up waiting at its grid
+                               barrier (lbm_ensemble_check): the members' states are invalid */
 };
 
 /* collision: LBGK eq. (LBGKmirr) or KBC eq. (ksh-mirror) */
@@ -136,9 +138,11 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
              const double* rho, const double* ux, const double* uy, const double* grad,
              int32_t mode);
 
-/* Advance nsteps >= 0 time steps of eq. (Egeneral): one fused pull-stream +
- * collide launch per step, alternating the two buffers.  Enqueues only; does
- * no value checks (see lbm_diagnostics). */
+/* Advance nsteps >= 0 time steps of eq. (Egeneral).  By default every pair of
+ * steps is one launch (two fused pull-stream + collide steps, the first step's
+ * result kept in LDS; see lbm_set_fusion) and an odd remainder one single-step
+ * launch; each launch reads one buffer and writes the other.  Enqueues only;
+ * does no value checks (see lbm_diagnostics). */
 int lbm_step(lbm_ctx* c, int32_t nsteps);
 
 /* Density, velocity and (optionally) the stabiliser gamma the next collision
@@ -221,11 +225,15 @@ int lbm_get_fusion(const lbm_ctx* c, int32_t* rows);
 int lbm_set_graph(lbm_ctx* c, int32_t chunk);
 int lbm_get_graph(const lbm_ctx* c);
 
-/* Replace beta (e.g. between rollouts); other parameters are fixed per ctx. */
+/* Replace beta (e.g. between rollouts); other parameters are fixed per ctx.
+ * An ensemble holding the context picks the new value up at its next
+ * lbm_ensemble_step. */
 int lbm_set_beta(lbm_ctx* c, double beta);
 
 /* Release the context and the scratch memory it allocated (never the
- * caller's buffers).  Synchronises the stream.  NULL is accepted. */
+ * caller's buffers).  Synchronises the stream.  NULL is accepted.
+ * LBM_EINVAL (and nothing is released) while the context is a member of a
+ * live ensemble: free the ensemble first. */
 int lbm_free(lbm_ctx* c);
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -310,7 +318,10 @@ int lbm_adjoint_init(lbm_ctx* c, const double* rho, const double* ux, const doub
  * form, collision, variant, stabiliser mode and stream)
  * and steps all of them; each member keeps its own buffers, parameters and
  * entry points (moments, populations, diagnostics).  Stepping is bitwise
- * identical to calling lbm_step on every member. */
+ * identical to calling lbm_step on every member.  A member cannot be freed
+ * while the ensemble lives (lbm_free returns LBM_EINVAL); a member's new beta
+ * (lbm_set_beta) is taken up at the next lbm_ensemble_step, which then
+ * rebuilds the member table (synchronising the stream). */
 typedef struct lbm_ens lbm_ens;
 
 int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count);
@@ -330,17 +341,48 @@ int lbm_ensemble_set_tile(lbm_ens* e, int32_t width, int32_t rows_per_thread, in
 int lbm_ensemble_set_fusion(lbm_ens* e, int32_t steps_per_launch, int32_t rows);
 int lbm_ensemble_get_fusion(const lbm_ens* e, int32_t* rows);
 
-/* Advance every member nsteps: persistent = 0 launches once per step (or per
- * pair of steps, see lbm_ensemble_set_fusion) over all members' tiles.  persistent = 1 (one cooperative launch of resident
- * workgroups looping over the steps with a grid-wide barrier in between) is
- * built but switched off and returns LBM_EUNSUPPORTED: its first run on the
- * GPU did not finish and the cause has not been shown.  All members must hold
- * their current state in the same buffer index (true when they have been
- * stepped equally since lbm_init). */
+/* Advance every member nsteps of eq. (Egeneral).
+ *   persistent = 0: one launch per step, or per pair of steps with
+ *     lbm_ensemble_set_fusion(2), over all members' tiles;
+ *   persistent = 1: ONE launch for all the steps (pairs of fused steps, or
+ *     single steps with fusion 1; an odd step left over by the pairs runs as
+ *     one more single-step launch): lbm_ensemble_blocks() workgroups, all
+ *     resident at once, each looping over its share of the tiles every step,
+ *     with a grid barrier (a device-memory arrival counter) between steps.
+ *     Every barrier wait is bounded by the spin limit
+ *     (lbm_ensemble_set_spin_limit): a workgroup that polls the counter that
+ *     many times marks the launch as failed and every wait of the launch then
+ *     ends at once, so the launch always terminates; lbm_ensemble_check
+ *     reports it (LBM_ESYNC).  Runs of more than (2^32 - 1) / blocks barriers
+ *     are split into several launches.
+ * Both modes run the single-lattice tile code on the same tiles: bitwise
+ * identical to lbm_step on every member.  All members must hold their
+ * current state in the same buffer index (true when they have been stepped
+ * equally since lbm_init).  Enqueues only (the persistent mode first resets
+ * the barrier state with a one-workgroup kernel on the same stream). */
 int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent);
 
-/* Workgroups of the persistent launch (resident capacity, a multiple of 8). */
+/* Grid size of the persistent launch for the current fusion and tiles: CU
+ * count x workgroups per CU, the smaller of the runtime's occupancy figure
+ * and the kernel's own limits (8 four-wave workgroups, the CU's LDS over the
+ * kernel's LDS, 512 registers over the kernel's register count), rounded
+ * down to a multiple of 8.  Negative on error. */
 int lbm_ensemble_blocks(const lbm_ens* e);
+
+/* Polls of the barrier counter after which a waiting workgroup of a
+ * persistent launch gives up (default LBM_ENSEMBLE_SPIN_DEFAULT, a few
+ * seconds; every poll is a device-scope load followed by a short sleep; at
+ * most LBM_ENSEMBLE_SPIN_MAX, else LBM_EINVAL).  0 gives up at the first poll
+ * that finds the barrier still closed: a host-side way to exercise the
+ * failure path. */
+#define LBM_ENSEMBLE_SPIN_DEFAULT (1u << 22)
+#define LBM_ENSEMBLE_SPIN_MAX (1u << 26)
+int lbm_ensemble_set_spin_limit(lbm_ens* e, uint32_t polls);
+
+/* Synchronises the stream and reports whether any persistent launch since
+ * the last check gave up at a barrier: LBM_OK, or LBM_ESYNC (the members'
+ * states are then invalid: re-initialise them).  Clears the flag. */
+int lbm_ensemble_check(lbm_ens* e);
 
 /* Release the ensemble (never the members).  Synchronises the stream. */
 int lbm_ensemble_free(lbm_ens* e);

@@ -14,7 +14,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libkbc.so")
 HEADER = os.path.join(os.path.dirname(PKG), "include", "kbc.h")
 
-LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENOMEM, LBM_ENONFINITE, LBM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENOMEM, LBM_ENONFINITE, LBM_EUNSUPPORTED, LBM_ESYNC = 0, -1, -2, -3, -4, -5, -6
+LBM_ENSEMBLE_SPIN_DEFAULT, LBM_ENSEMBLE_SPIN_MAX = 1 << 22, 1 << 26
 LBGK, KBC = 0, 1
 KBC_A, KBC_B, KBC_C, KBC_D = 0, 1, 2, 3
 F16DEV_F32, F32DEV_F32, F64 = 0, 1, 2
@@ -78,6 +79,8 @@ _SIGS = {
     "lbm_ensemble_set_fusion": (_c.c_int, [_vp, _c.c_int32, _c.c_int32]),
     "lbm_ensemble_get_fusion": (_c.c_int, [_vp, _c.POINTER(_c.c_int32)]),
     "lbm_ensemble_blocks": (_c.c_int, [_vp]),
+    "lbm_ensemble_set_spin_limit": (_c.c_int, [_vp, _c.c_uint32]),
+    "lbm_ensemble_check": (_c.c_int, [_vp]),
     "lbm_ensemble_free": (_c.c_int, [_vp]),
     "lbm_set_adjoint_gamma": (_c.c_int, [_vp, _c.c_int32]),
     "lbm_adjoint_bytes": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),

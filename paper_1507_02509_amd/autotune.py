@@ -6,7 +6,8 @@ stores) and the two-step fused kernel with each tile height and store kind --
 on the caller's own lattice with HIP events; for an ensemble, every tile of
 the ensemble kernel.  It keeps the one with the smallest median time and
 caches the choice in a JSON file keyed by the device name and the
-configuration (form, collision, variant, lattice sizes).
+configuration (form, collision, variant, stabiliser mode and guard, lattice
+sizes).
 The lattice state is restored afterwards: every trial takes an even number of
 steps and the state buffers are copied back, so tuning changes nothing but
 the tile.  Results of the step kernels are bitwise identical for every tile,
@@ -79,9 +80,15 @@ def _time(run, steps: int, reps: int) -> float:
     return times[len(times) // 2]
 
 
+def _model_key(params) -> list[str]:
+    # the stabiliser mode and guard change the per-node cost (the exact root
+    # runs a Newton iteration), so a choice made for one is not reused for another
+    return [str(params.collision), str(params.variant), f"gm{params.gamma_mode}", f"guard{params.gamma_guard:.3e}"]
+
+
 def _sim_key(sim) -> str:
-    return "|".join(["sim2", torch.cuda.get_device_name(sim.device), str(sim.form), str(sim.params.collision),
-                     str(sim.params.variant), f"{sim.nx}x{sim.ny}"])
+    return "|".join(["sim3", torch.cuda.get_device_name(sim.device), str(sim.form), *_model_key(sim.params),
+                     f"{sim.nx}x{sim.ny}"])
 
 
 def tune_sim(sim, steps: int = 10, reps: int = 3, candidates=None, use_cache: bool = True):
@@ -130,8 +137,8 @@ def apply_ensemble_config(ens, cand):
 def _ens_key(ens) -> str:
     m0 = ens.members[0]
     sizes = hashlib.sha1(",".join(f"{m.nx}x{m.ny}" for m in ens.members).encode()).hexdigest()[:12]
-    return "|".join(["ensemble2", torch.cuda.get_device_name(m0.device), str(m0.form), str(m0.params.collision),
-                     str(m0.params.variant), str(len(ens.members)), sizes])
+    return "|".join(["ensemble3", torch.cuda.get_device_name(m0.device), str(m0.form), *_model_key(m0.params),
+                     str(len(ens.members)), sizes])
 
 
 def tune_ensemble(ens, steps: int = 10, reps: int = 3, persistent: bool = False, candidates=None,

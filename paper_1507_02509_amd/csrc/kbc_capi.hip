@@ -35,6 +35,9 @@ struct lbm_ctx {
     hipStream_t cap_stream; // private stream the graphs are captured on
     hipGraphExec_t gexec[2];  // captured graph_chunk steps, by the buffer holding the start state
     int gnext[2];           // buffer holding the state after one replay
+    int ens_refs;           // live ensembles holding this context (lbm_free refuses while > 0)
+    uint64_t gen;           // parameter generation: bumped when beta changes, so that an
+                            // ensemble holding the context rebuilds its member table
 };
 
 namespace {
@@ -159,9 +162,9 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     c->cur = 0;
     c->steps = 0;
     c->shape = default_shape(p->form);
-    // two fused steps per launch by default where that is faster (measured:
-    // FP32 +38 %, FP64 +25 % for KBC-B at 16384^2); FP16 is limited by
-    // arithmetic, which the ring of extra collisions only adds to
+    // two fused steps per launch by default for every form (measured for
+    // KBC-B at 16384^2: FP32 +38 %, FP64 +25 %, FP16 +6 % over single steps;
+    // the ring of extra step-1 collisions costs less than the HBM pass it saves)
     c->fuse = 2;
     c->fuse_rows = (p->form == LBM_F64) ? 8 : 16;
     // small lattices: fewer than 1024 tiles of 16 rows leave most CUs with one
@@ -179,6 +182,8 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     c->gexec[0] = c->gexec[1] = nullptr;
     c->gnext[0] = 0;
     c->gnext[1] = 1;
+    c->ens_refs = 0;
+    c->gen = 0;
     rc = kbc::launch_init(c->L, buf_a, rho, ux, uy, grad, mode);
     if (rc) {
         delete c;
@@ -426,6 +431,7 @@ int lbm_set_beta(lbm_ctx* c, double beta) {
     if (beta != c->p.beta) {
         const int rc = graph_reset(c);
         if (rc) return rc;
+        ++c->gen;
     }
     c->p.beta = beta;
     c->L.beta = beta;
@@ -434,6 +440,8 @@ int lbm_set_beta(lbm_ctx* c, double beta) {
 
 int lbm_free(lbm_ctx* c) {
     if (!c) return LBM_OK;
+    if (c->ens_refs > 0)
+        return fail(LBM_EINVAL, "context is a member of %d live ensemble(s): free them first", c->ens_refs);
     int rc = LBM_OK;
     if (c->dscratch || c->ascratch || c->sscratch || c->fft_plan || c->gexec[0] || c->gexec[1] || c->cap_stream) {
         hipError_t e = hipStreamSynchronize(c->L.stream);
@@ -650,7 +658,8 @@ struct lbm_ens {
     kbc::StepShape shape;
     kbc::EnsEntry* dtab;        // member table for single-step tiles
     int ntiles;
-    int blocks;                 // resident workgroups for the persistent launch
+    kbc::EnsSync* dsync;        // grid-barrier state of the persistent launches
+    uint32_t spin_limit;        // polls of the barrier counter before a persistent launch gives up
     int fuse;                   // steps per launch: 1 or 2
     int rows;                   // fused tile height: 8 or 16
     kbc::EnsEntry* dtab2;       // member table for fused 64 x rows tiles
@@ -659,9 +668,12 @@ struct lbm_ens {
     int64_t dmap2_len;
     int32_t* dmap;              // member of each single-step tile
     int64_t dmap_len;
+    std::vector<uint64_t> gens; // member parameter generations the tables were built from
 };
 
 namespace {
+
+const kbc::EnsSync kZeroSync{};
 
 bool ens_shape_ok(const kbc::StepShape& s) {
     return ((s.width == 128 && s.rpt == 2) || (s.width == 256 && (s.rpt == 1 || s.rpt == 2))) &&
@@ -751,10 +763,9 @@ int ens_build(lbm_ens* e) {
     rc = ens_map(e, tab, tiles, &e->dmap, &e->dmap_len);
     if (rc) return rc;
     e->ntiles = static_cast<int>(tiles);
-    kbc::EnsLaunch a{};
-    a.shape = e->shape;
-    a.query_blocks = &e->blocks;
-    return launch_result(kbc::launch_ensemble(e->L, a), "ensemble occupancy");
+    e->gens.resize(e->m.size());
+    for (size_t r = 0; r < e->m.size(); ++r) e->gens[r] = e->m[r]->gen;
+    return LBM_OK;
 }
 
 }  // namespace
@@ -789,12 +800,19 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
     e->dmap2_len = 0;
     e->dmap = nullptr;
     e->dmap_len = 0;
-    e->blocks = 0;
+    e->dsync = nullptr;
+    e->spin_limit = LBM_ENSEMBLE_SPIN_DEFAULT;
     // two fused steps per launch, as for single lattices
     e->fuse = 2;
     e->rows = (m0->p.form == LBM_F64) ? 8 : 16;
     int rc = ens_build(e);
+    if (!rc) {
+        hipError_t err = hipMalloc(&e->dsync, sizeof(kbc::EnsSync));
+        if (err == hipSuccess) err = hipMemcpy(e->dsync, &kZeroSync, sizeof(kbc::EnsSync), hipMemcpyHostToDevice);
+        if (err != hipSuccess) rc = fail(LBM_ENOMEM, "ensemble barrier state: %s", hipGetErrorString(err));
+    }
     if (rc) {
+        if (e->dsync) (void)hipFree(e->dsync);
         if (e->dtab) (void)hipFree(e->dtab);
         if (e->dtab2) (void)hipFree(e->dtab2);
         if (e->dmap2) (void)hipFree(e->dmap2);
@@ -802,6 +820,7 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
         delete e;
         return rc;
     }
+    for (lbm_ctx* c : e->m) ++c->ens_refs;
     *out = e;
     return LBM_OK;
 }
@@ -818,16 +837,56 @@ int lbm_ensemble_set_tile(lbm_ens* e, int32_t width, int32_t rows_per_thread, in
     return ens_build(e);
 }
 
-int lbm_ensemble_blocks(const lbm_ens* e) { return e ? e->blocks : -1; }
+int lbm_ensemble_blocks(const lbm_ens* e) {
+    if (!e) return fail(LBM_EINVAL, "ensemble is NULL");
+    int blocks = 0;
+    kbc::EnsLaunch a{};
+    a.shape = e->shape;
+    a.rows = e->rows;
+    a.query_blocks = &blocks;
+    const int rc = (e->fuse == 2) ? kbc::launch_ensemble2(e->L, a) : kbc::launch_ensemble(e->L, a);
+    if (rc) return launch_result(rc, "lbm_ensemble_blocks");
+    return blocks;
+}
+
+int lbm_ensemble_set_spin_limit(lbm_ens* e, uint32_t polls) {
+    if (!e) return fail(LBM_EINVAL, "ensemble is NULL");
+    if (polls > LBM_ENSEMBLE_SPIN_MAX)
+        return fail(LBM_EINVAL, "spin limit %u above the maximum %u", polls, LBM_ENSEMBLE_SPIN_MAX);
+    e->spin_limit = polls;
+    return LBM_OK;
+}
+
+int lbm_ensemble_check(lbm_ens* e) {
+    if (!e) return fail(LBM_EINVAL, "ensemble is NULL");
+    hipError_t err = hipStreamSynchronize(e->L.stream);
+    if (err != hipSuccess) return hip_fail(err, "lbm_ensemble_check sync");
+    uint32_t failed = 0;
+    err = hipMemcpy(&failed, &e->dsync->failed, sizeof failed, hipMemcpyDeviceToHost);
+    if (err != hipSuccess) return hip_fail(err, "lbm_ensemble_check read");
+    if (!failed) return LBM_OK;
+    const uint32_t zero = 0;
+    err = hipMemcpy(&e->dsync->failed, &zero, sizeof zero, hipMemcpyHostToDevice);
+    if (err != hipSuccess) return hip_fail(err, "lbm_ensemble_check clear");
+    return fail(LBM_ESYNC,
+                "a persistent ensemble launch gave up at a grid barrier (not every workgroup was resident "
+                "within the spin limit); the members' states are invalid");
+}
 
 int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent) {
     if (!e) return fail(LBM_EINVAL, "ensemble is NULL");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
-    if (persistent)
-        return fail(LBM_EUNSUPPORTED,
-                    "the persistent (cooperative, grid-barrier) ensemble launch is switched off: its first GPU run "
-                    "did not finish and no cause has been shown; use persistent = 0 (one launch per step)");
+    if (persistent != 0 && persistent != 1) return fail(LBM_EINVAL, "persistent must be 0 or 1");
     if (nsteps == 0) return LBM_OK;
+    // a member whose parameters changed since the tables were built (e.g.
+    // lbm_set_beta): rebuild them, so the ensemble keeps stepping exactly as
+    // lbm_step on every member would
+    for (size_t r = 0; r < e->m.size(); ++r)
+        if (e->m[r]->gen != e->gens[r]) {
+            const int rc = ens_build(e);
+            if (rc) return rc;
+            break;
+        }
     const int cur = e->m[0]->cur;
     for (size_t r = 1; r < e->m.size(); ++r)
         if (e->m[r]->cur != cur) return fail(LBM_EINVAL, "members hold their states in different buffers");
@@ -835,8 +894,8 @@ int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent) {
     const int singles = nsteps - 2 * pairs;
     kbc::EnsLaunch a{};
     a.nmem = static_cast<int>(e->m.size());
-    a.persistent = false;
-    a.blocks = e->blocks;
+    a.sync = e->dsync;
+    a.spin_limit = e->spin_limit;
     a.shape = e->shape;
     a.stream = e->L.stream;
     a.rows = e->rows;
@@ -847,6 +906,7 @@ int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent) {
         a.ntiles = e->ntiles2;
         a.nsteps = pairs;
         a.parity = par;
+        a.persistent = persistent != 0;
         const int rc = kbc::launch_ensemble2(e->L, a);
         if (rc) return launch_result(rc, "lbm_ensemble_step (two fused steps)");
         par ^= (pairs & 1);
@@ -857,6 +917,8 @@ int lbm_ensemble_step(lbm_ens* e, int32_t nsteps, int32_t persistent) {
         a.ntiles = e->ntiles;
         a.nsteps = singles;
         a.parity = par;
+        // one leftover single step after pairs is an ordinary launch
+        a.persistent = persistent != 0 && singles > 1;
         const int rc = kbc::launch_ensemble(e->L, a);
         if (rc) return launch_result(rc, "lbm_ensemble_step");
         par ^= (singles & 1);
@@ -890,14 +952,16 @@ int lbm_ensemble_get_fusion(const lbm_ens* e, int32_t* rows) {
 int lbm_ensemble_free(lbm_ens* e) {
     if (!e) return LBM_OK;
     int rc = LBM_OK;
-    if (e->dtab || e->dtab2 || e->dmap2 || e->dmap) {
+    if (e->dtab || e->dtab2 || e->dmap2 || e->dmap || e->dsync) {
         hipError_t err = hipStreamSynchronize(e->L.stream);
         if (err != hipSuccess) rc = hip_fail(err, "lbm_ensemble_free sync");
+        if (e->dsync) (void)hipFree(e->dsync);
         if (e->dtab) (void)hipFree(e->dtab);
         if (e->dtab2) (void)hipFree(e->dtab2);
         if (e->dmap2) (void)hipFree(e->dmap2);
         if (e->dmap) (void)hipFree(e->dmap);
     }
+    for (lbm_ctx* c : e->m) --c->ens_refs;
     delete e;
     return rc;
 }

@@ -3,24 +3,34 @@
 //
 // A device table lists the members (buffers, size, pitch, beta) and the first
 // index of each member's tiles in one global tile numbering (members in order,
-// row-major tiles within a member); a per-tile index gives each tile's member.  The tile range is cut into eight equal
-// contiguous bands, one per XCD (workgroup b runs on XCD b % 8), and the
-// workgroups of an XCD deal its band out round-robin, so x-neighbour tiles of
-// one member meet in the same L2 as in the single-lattice step.
+// row-major tiles within a member); a per-tile index gives each tile's member.
+// The tile range is cut into eight equal contiguous bands, one per XCD
+// (workgroup b runs on XCD b % 8), and the workgroups of an XCD deal its band
+// out round-robin, so x-neighbour tiles of one member meet in the same L2 as in
+// the single-lattice step.
 //
-// The same kernel runs in two modes:
-//   * one launch per step (nsteps = 1): one workgroup per tile;
-//   * one persistent cooperative launch for many steps: as many workgroups as
-//     can be resident, looping over their tiles each step, with a grid-wide
-//     barrier between steps (cooperative groups; the barrier's device-scope
-//     fences make the new states of every XCD visible to all others).
-// Both modes run the per-node code of the single-lattice step on the same
+// Launch modes:
+//   * k_ens: one launch per step, one workgroup per tile (tile body of the
+//     single-lattice step, kbc_tile.hpp);
+//   * k_ens2: one launch per two fused steps, one workgroup per 64 x TH output
+//     tile (tile body of the single-lattice fused kernel, kbc_tile2.hpp);
+//   * k_ens_persist / k_ens2_persist: ONE launch for many steps (or pairs of
+//     steps): as many workgroups as the GPU holds at once, each looping over
+//     its share of the tiles every step, with a grid barrier between steps.
+// All of them run the per-node code of the single-lattice step on the same
 // tiles, so results are bitwise identical to stepping each member alone.
 //
-// k_ens2 advances every member by two fused steps per launch (the tile body
-// of the single-lattice fused kernel, 64 x TH output tiles, one workgroup per
-// tile), again bitwise identical to single steps.
-#include <hip/hip_cooperative_groups.h>
+// The grid barrier (grid_barrier) is an arrival counter in device memory: a
+// workgroup finishing step s adds one and waits until the counter reaches
+// (s + 1) x (grid size).  That wait ends only if every workgroup of the grid is
+// resident at the same time, so the grid is capped at the resident capacity
+// computed from both the runtime's occupancy figure and the kernel's own LDS
+// and register use (resident_blocks).  As a safeguard the wait is bounded: a
+// workgroup that has polled the counter `spin_limit` times sets a give-up flag,
+// after which every wait of the launch returns at once, so the launch always
+// ends; the host reads the sticky flag (lbm_ensemble_check) and reports the
+// states as invalid.
+#include <algorithm>
 
 #include "kbc_launch.hpp"
 #include "kbc_tile.hpp"
@@ -30,37 +40,74 @@ namespace kbc {
 
 namespace {
 
+template <typename R>
+__device__ __forceinline__ Coef<R> coef_of(const EnsEntry& e) {
+    Coef<R> K;
+    K.beta = static_cast<R>(e.beta);
+    K.inv_beta = static_cast<R>(e.inv_beta);
+    K.two_m_inv_beta = static_cast<R>(e.two_m_inv_beta);
+    K.rho0 = static_cast<R>(e.rho0);
+    K.guard = static_cast<R>(e.guard);
+    K.gamma_fixed = static_cast<R>(e.gamma_fixed);
+    return K;
+}
+
+// Barrier over the whole grid of a persistent launch, the `target`-th
+// arrival of every workgroup ending it (target = (s + 1) x grid size after
+// step s).  Memory order: every wave first waits until its own stores of the
+// step have completed (they are then in the L2 of its XCD); after a workgroup
+// barrier one thread makes them visible at device scope (release fence: the
+// L2 is written back), counts the workgroup in and polls the counter with
+// device-scope atomics, then drops cached lines that another XCD may have
+// rewritten (acquire fence: the CU's L1 and the non-coherent L2 lines are
+// invalidated) before the workgroup goes on.  One write-back and one
+// invalidation per workgroup, not per wave: each acts on a whole cache.
+__device__ __forceinline__ void grid_barrier(EnsSync* sy, uint32_t target, uint32_t spin_limit) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&sy->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (uint32_t it = 0;; ++it) {
+            if (__hip_atomic_load(&sy->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+            if (it >= spin_limit) {
+                __hip_atomic_store(&sy->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&sy->failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Clears the arrival counter and the give-up flag before a persistent launch
+// (the sticky `failed` word is left for the host).
+__global__ void k_sync_reset(EnsSync* sy) {
+    if (threadIdx.x == 0) {
+        sy->count = 0u;
+        sy->abort = 0u;
+    }
+}
+
 template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_ens(const EnsEntry* __restrict__ tab,
-                                             const int32_t* __restrict__ tile_member, int ntiles, int nsteps,
+                                             const int32_t* __restrict__ tile_member, int ntiles, int per_xcd,
                                              int parity) {
     using F = Form<FORM>;
     using S = typename F::S;
     using R = typename F::R;
-    const int xcd = static_cast<int>(blockIdx.x & 7u), j = static_cast<int>(blockIdx.x >> 3);
-    const int m = static_cast<int>(gridDim.x >> 3);
-    const int band = (ntiles + 7) >> 3;
-    const int start = xcd * band;
-    const int end = (start + band < ntiles) ? start + band : ntiles;
-    for (int s = 0; s < nsteps; ++s) {
-        const int par = (parity + s) & 1;
-        for (int t = start + j; t < end; t += m) {
-            // member holding tile t, from the per-tile index (one scalar load)
-            const EnsEntry& e = tab[tile_member[t]];
-            Coef<R> K;
-            K.beta = static_cast<R>(e.beta);
-            K.inv_beta = static_cast<R>(e.inv_beta);
-            K.two_m_inv_beta = static_cast<R>(e.two_m_inv_beta);
-            K.rho0 = static_cast<R>(e.rho0);
-            K.guard = static_cast<R>(e.guard);
-            K.gamma_fixed = static_cast<R>(e.gamma_fixed);
-            const int lt = t - e.tile_start;
-            step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT>(
-                static_cast<const S*>(e.buf[par]), static_cast<S*>(e.buf[par ^ 1]), e.nx, e.ny, e.pitch,
-                lt % e.ntx, lt / e.ntx, K);
-        }
-        if (s + 1 < nsteps) cooperative_groups::this_grid().sync();
-    }
+    const int b = blockIdx.x;
+    const int t = (b & 7) * per_xcd + (b >> 3);
+    if (t >= ntiles) return;
+    // member holding tile t, from the per-tile index (one scalar load)
+    const EnsEntry& e = tab[tile_member[t]];
+    const int lt = t - e.tile_start;
+    step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT>(static_cast<const S*>(e.buf[parity]),
+                                                 static_cast<S*>(e.buf[parity ^ 1]), e.nx, e.ny, e.pitch,
+                                                 lt % e.ntx, lt / e.ntx, coef_of<R>(e));
 }
 
 // The member of tile t comes from a per-tile index (one scalar load) rather
@@ -77,23 +124,131 @@ __global__ __launch_bounds__(256) void k_ens2(const EnsEntry* __restrict__ tab,
     const int t = (b & 7) * per_xcd + (b >> 3);
     if (t >= ntiles) return;   // the whole workgroup leaves together
     const EnsEntry& e = tab[tile_member[t]];
-    Coef<R> K;
-    K.beta = static_cast<R>(e.beta);
-    K.inv_beta = static_cast<R>(e.inv_beta);
-    K.two_m_inv_beta = static_cast<R>(e.two_m_inv_beta);
-    K.rho0 = static_cast<R>(e.rho0);
-    K.guard = static_cast<R>(e.guard);
-    K.gamma_fixed = static_cast<R>(e.gamma_fixed);
     const int lt = t - e.tile_start;
     step2_tile<FORM, COLL, VAR, GM, TH, NT>(static_cast<const S*>(e.buf[parity]), static_cast<S*>(e.buf[parity ^ 1]),
-                                            e.nx, e.ny, e.pitch, (lt % e.ntx) * 64, (lt / e.ntx) * TH, K);
+                                            e.nx, e.ny, e.pitch, (lt % e.ntx) * 64, (lt / e.ntx) * TH,
+                                            coef_of<R>(e));
 }
 
-// one fused launch per two steps: a.nsteps launches, each src -> dst
+// Persistent single steps: workgroup j of XCD x takes tiles x band + j,
+// x band + j + m, ... (m workgroups per XCD) of every step.
+template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
+__global__ __launch_bounds__(256) void k_ens_persist(const EnsEntry* __restrict__ tab,
+                                                     const int32_t* __restrict__ tile_member, int ntiles,
+                                                     int nsteps, int parity, EnsSync* sync, uint32_t spin_limit) {
+    using F = Form<FORM>;
+    using S = typename F::S;
+    using R = typename F::R;
+    const int xcd = static_cast<int>(blockIdx.x & 7u), j = static_cast<int>(blockIdx.x >> 3);
+    const int m = static_cast<int>(gridDim.x >> 3);
+    const int band = (ntiles + 7) >> 3;
+    const int start = xcd * band;
+    const int end = (start + band < ntiles) ? start + band : ntiles;
+    for (int s = 0; s < nsteps; ++s) {
+        const int par = (parity + s) & 1;
+        for (int t = start + j; t < end; t += m) {
+            const EnsEntry& e = tab[tile_member[t]];
+            const int lt = t - e.tile_start;
+            step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT>(static_cast<const S*>(e.buf[par]),
+                                                         static_cast<S*>(e.buf[par ^ 1]), e.nx, e.ny, e.pitch,
+                                                         lt % e.ntx, lt / e.ntx, coef_of<R>(e));
+        }
+        if (s + 1 < nsteps) grid_barrier(sync, static_cast<uint32_t>(s + 1) * gridDim.x, spin_limit);
+    }
+}
+
+// Persistent pairs of fused steps; the tile body holds a workgroup barrier
+// and reuses the LDS windows, so consecutive tiles of a workgroup are
+// separated by one more barrier.
+template <int FORM, int COLL, int VAR, int GM, int TH, bool NT>
+__global__ __launch_bounds__(256) void k_ens2_persist(const EnsEntry* __restrict__ tab,
+                                                      const int32_t* __restrict__ tile_member, int ntiles,
+                                                      int npairs, int parity, EnsSync* sync, uint32_t spin_limit) {
+    using F = Form<FORM>;
+    using S = typename F::S;
+    using R = typename F::R;
+    const int xcd = static_cast<int>(blockIdx.x & 7u), j = static_cast<int>(blockIdx.x >> 3);
+    const int m = static_cast<int>(gridDim.x >> 3);
+    const int band = (ntiles + 7) >> 3;
+    const int start = xcd * band;
+    const int end = (start + band < ntiles) ? start + band : ntiles;
+    for (int s = 0; s < npairs; ++s) {
+        const int par = (parity + s) & 1;
+        for (int t = start + j; t < end; t += m) {
+            const EnsEntry& e = tab[tile_member[t]];
+            const int lt = t - e.tile_start;
+            step2_tile<FORM, COLL, VAR, GM, TH, NT>(static_cast<const S*>(e.buf[par]),
+                                                    static_cast<S*>(e.buf[par ^ 1]), e.nx, e.ny, e.pitch,
+                                                    (lt % e.ntx) * 64, (lt / e.ntx) * TH, coef_of<R>(e));
+            __syncthreads();
+        }
+        if (s + 1 < npairs) grid_barrier(sync, static_cast<uint32_t>(s + 1) * gridDim.x, spin_limit);
+    }
+}
+
+// Workgroups of 256 threads that the GPU holds at once for `kern`, a multiple
+// of 8 (one band per XCD): CUs x the smaller of the runtime's occupancy figure
+// and the kernel's own limits -- 8 workgroups of four waves per CU (eight
+// waves per SIMD), the LDS of a CU over the workgroup's static LDS, and the
+// 512 vector registers of a SIMD lane over the kernel's register count.
+// Returns 0 on failure.
+int resident_blocks(const void* kern) {
+    int dev = 0, cus = 0, lds_cu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) != hipSuccess) return 0;
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, kern) != hipSuccess) return 0;
+    int own = 8;
+    if (fa.sharedSizeBytes > 0) {
+        const int granule = 512;
+        const int lds = static_cast<int>((fa.sharedSizeBytes + granule - 1) / granule * granule);
+        own = std::min(own, lds_cu / lds);
+    }
+    if (fa.numRegs > 0) own = std::min(own, 512 / ((fa.numRegs + 7) / 8 * 8));
+    per_cu = std::min(per_cu, own);
+    if (per_cu < 1 || cus < 1) return 0;
+    return (per_cu * cus) / 8 * 8;
+}
+
+// One persistent launch per chunk of steps: the arrival counter is 32-bit, so
+// a chunk holds at most (2^32 - 1) / blocks barriers.
+template <typename Kern>
+int launch_persistent(Kern kern, const EnsLaunch& a, int blocks) {
+    if (!a.sync || blocks < 8 || blocks % 8) return -1;
+    const int64_t max_chunk = static_cast<int64_t>(0xffffffffu) / blocks;
+    const EnsEntry* tab = a.table;
+    const int32_t* map = a.tile_member;
+    int done = 0;
+    while (done < a.nsteps) {
+        const int n = static_cast<int>(std::min<int64_t>(a.nsteps - done, max_chunk));
+        k_sync_reset<<<1, 64, 0, a.stream>>>(a.sync);
+        if (hipGetLastError() != hipSuccess) return -2;
+        kern<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, a.stream>>>(tab, map, a.ntiles, n,
+                                                                            (a.parity + done) & 1, a.sync,
+                                                                            a.spin_limit);
+        if (hipGetLastError() != hipSuccess) return -2;
+        done += n;
+    }
+    return 0;
+}
+
+// a.nsteps launches of two fused steps (or, persistent, one launch for all of them)
 template <int FORM, int COLL, int VAR, int GM>
 struct Ens2Op {
     template <int TH, bool NT>
     static int go(const EnsLaunch& a) {
+        if (a.persistent || a.query_blocks) {
+            auto kern = k_ens2_persist<FORM, COLL, VAR, GM, TH, NT>;
+            const int blocks = resident_blocks(reinterpret_cast<const void*>(kern));
+            if (a.query_blocks) {
+                *a.query_blocks = blocks;
+                return blocks > 0 ? 0 : -2;
+            }
+            return launch_persistent(kern, a, blocks);
+        }
         const int per_xcd = (a.ntiles + 7) / 8;
         for (int s = 0; s < a.nsteps; ++s) {
             const int par = (a.parity + s) & 1;
@@ -105,7 +260,7 @@ struct Ens2Op {
     }
     static int run(const Lattice& L, const EnsLaunch& a) {
         (void)L;
-        if (!a.tile_member) return -1;
+        if (!a.tile_member && !a.query_blocks) return -1;
         switch (a.rows * 2 + (a.shape.nt ? 1 : 0)) {
             case 8 * 2: return go<8, false>(a);
             case 8 * 2 + 1: return go<8, true>(a);
@@ -116,46 +271,32 @@ struct Ens2Op {
     }
 };
 
+// a.nsteps single steps: one launch each (or, persistent, one launch for all)
 template <int FORM, int COLL, int VAR, int GM>
 struct EnsOp {
     template <int TXW, int RPT, bool NT>
     static int go(const EnsLaunch& a) {
-        auto kern = k_ens<FORM, COLL, VAR, GM, TXW, RPT, NT>;
-        if (a.query_blocks) {
-            int per_cu = 0, dev = 0, cus = 0;
-            if (hipGetDevice(&dev) != hipSuccess) return -2;
-            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -2;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 256, 0) !=
-                hipSuccess)
-                return -2;
-            *a.query_blocks = (per_cu * cus) / 8 * 8;
-            return 0;
-        }
-        const EnsEntry* tab = a.table;
-        const int32_t* map = a.tile_member;
-        int ntiles = a.ntiles, nsteps = a.nsteps, parity = a.parity;
-        if (!map) return -1;
-        if (!a.persistent) {
-            const int band = (ntiles + 7) / 8;
-            for (int s = 0; s < nsteps; ++s) {
-                const int one = 1, par = (parity + s) & 1;
-                kern<<<dim3(8u * static_cast<unsigned>(band)), dim3(256), 0, a.stream>>>(tab, map, ntiles, one, par);
-                if (hipGetLastError() != hipSuccess) return -2;
+        if (a.persistent || a.query_blocks) {
+            auto kern = k_ens_persist<FORM, COLL, VAR, GM, TXW, RPT, NT>;
+            const int blocks = resident_blocks(reinterpret_cast<const void*>(kern));
+            if (a.query_blocks) {
+                *a.query_blocks = blocks;
+                return blocks > 0 ? 0 : -2;
             }
-            return 0;
+            return launch_persistent(kern, a, blocks);
         }
-        if (a.blocks < 8 || a.blocks % 8) return -1;
-        void* args[] = {&tab, &map, &ntiles, &nsteps, &parity};
-        if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(static_cast<unsigned>(a.blocks)),
-                                       dim3(256), args, 0, a.stream) != hipSuccess)
-            return -2;
+        const int per_xcd = (a.ntiles + 7) / 8;
+        for (int s = 0; s < a.nsteps; ++s) {
+            const int par = (a.parity + s) & 1;
+            k_ens<FORM, COLL, VAR, GM, TXW, RPT, NT><<<dim3(8u * static_cast<unsigned>(per_xcd)), dim3(256), 0,
+                                                       a.stream>>>(a.table, a.tile_member, a.ntiles, per_xcd, par);
+            if (hipGetLastError() != hipSuccess) return -2;
+        }
         return 0;
     }
     static int run(const Lattice& L, const EnsLaunch& a) {
         (void)L;
-        return shapes(a);
-    }
-    static int shapes(const EnsLaunch& a) {
+        if (!a.tile_member && !a.query_blocks) return -1;
         const StepShape& sh = a.shape;
         const int key = sh.width * 16 + sh.rpt;
         if (sh.nt) {

@@ -56,16 +56,30 @@ struct EnsEntry {
     int64_t pitch;
     double beta, inv_beta, two_m_inv_beta, rho0, guard, gamma_fixed;
 };
+// Grid-barrier state of a persistent ensemble launch (device memory owned by
+// the ensemble): the arrival counter and this launch's give-up flag are reset
+// by a small kernel before every persistent launch; `failed` is sticky until
+// the host reads it (lbm_ensemble_check).  Each word has a 128-byte line of
+// its own.
+struct EnsSync {
+    uint32_t count;
+    uint32_t pad0[31];
+    uint32_t abort;
+    uint32_t pad1[31];
+    uint32_t failed;
+    uint32_t pad2[31];
+};
 struct EnsLaunch {
     const EnsEntry* table;  // device copy of the member table
     int nmem, ntiles, nsteps, parity;
-    bool persistent;        // one cooperative launch for all nsteps
-    int blocks;             // persistent grid size (multiple of 8)
+    bool persistent;        // one launch of resident workgroups for all nsteps
+    EnsSync* sync;          // persistent: barrier state
+    uint32_t spin_limit;    // persistent: polls of the barrier counter before giving up
     StepShape shape;        // (128,2), (256,1) or (256,2), with or without nt
     hipStream_t stream;
-    int* query_blocks;      // if set: only report the resident-workgroup count
+    int* query_blocks;      // if set: only report the persistent launch's grid size
     int rows;               // fused launches: output tile height (8 or 16)
-    const int32_t* tile_member;   // fused launches: member of each tile (device)
+    const int32_t* tile_member;   // member of each tile (device)
 };
 int launch_ensemble(const Lattice& L, const EnsLaunch& a);
 // two fused steps per launch for every member; a.nsteps counts launches, the

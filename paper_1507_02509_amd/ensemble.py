@@ -28,7 +28,21 @@ class Ensemble:
 
     @property
     def blocks(self) -> int:
-        return int(self.lib.lbm_ensemble_blocks(self.h))
+        """Grid size of the persistent launch for the current fusion and tiles."""
+        b = int(self.lib.lbm_ensemble_blocks(self.h))
+        if b < 0:
+            L.check(b, "lbm_ensemble_blocks")
+        return b
+
+    def set_spin_limit(self, polls: int):
+        """Barrier polls after which a persistent launch gives up (see check())."""
+        L.check(self.lib.lbm_ensemble_set_spin_limit(self.h, int(polls)), "lbm_ensemble_set_spin_limit")
+
+    def check(self) -> "Ensemble":
+        """Synchronise and raise KbcError (LBM_ESYNC) if a persistent launch
+        since the last check gave up at a grid barrier."""
+        L.check(self.lib.lbm_ensemble_check(self.h), "lbm_ensemble_check")
+        return self
 
     def set_tile(self, width: int, rows_per_thread: int, nontemporal: bool = False):
         L.check(self.lib.lbm_ensemble_set_tile(self.h, int(width), int(rows_per_thread), 1 if nontemporal else 0),
@@ -44,6 +58,8 @@ class Ensemble:
         return int(self.lib.lbm_ensemble_get_fusion(self.h, None))
 
     def step(self, n: int = 1, persistent: bool = False) -> "Ensemble":
+        """n steps of every member: one launch per step (or pair of fused
+        steps), or with persistent=True one launch for all of them."""
         L.check(self.lib.lbm_ensemble_step(self.h, int(n), 1 if persistent else 0), "lbm_ensemble_step")
         return self
 

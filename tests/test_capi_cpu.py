@@ -106,3 +106,13 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(ImportError, match="no CPU fallback"):
         L.load()
+
+
+def test_ensemble_entry_points_reject_null(lib):
+    """The ensemble calls validate their handle before any HIP call."""
+    assert lib.lbm_ensemble_step(None, 2, 1) == L.LBM_EINVAL
+    assert lib.lbm_ensemble_set_spin_limit(None, 5) == L.LBM_EINVAL
+    assert lib.lbm_ensemble_check(None) == L.LBM_EINVAL
+    assert lib.lbm_ensemble_blocks(None) < 0
+    assert lib.lbm_ensemble_free(None) == L.LBM_OK
+    assert L.LBM_ESYNC == -6 and L.LBM_ENSEMBLE_SPIN_MAX == 1 << 26

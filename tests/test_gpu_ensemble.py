@@ -1,6 +1,6 @@
 """GPU tests of the ensemble kernels (uneven lattices in one launch, single
-or two fused steps per launch; the persistent cooperative launch is switched
-off) and of the tile autotuner.
+or two fused steps per launch, or one persistent launch for many steps with a
+bounded grid barrier) and of the tile autotuner.
 The per-node code is shared with the single-lattice step, so an ensemble step
 must equal stepping every member alone, bit for bit."""
 import sys
@@ -25,10 +25,6 @@ def say(*a):
 def _gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-
-
-PERSISTENT_OFF = ("persistent cooperative launch switched off: its first GPU run did not finish and no "
-                  "cause has been shown")
 
 
 def small_specs():
@@ -92,38 +88,113 @@ def test_ensemble_members_match_oracle(orc):
         assert err < 1e-12, (nx, ny, err)
 
 
-def test_persistent_mode_is_refused():
+def test_member_beta_change_and_member_lifetime():
+    """A member's new beta (lbm_set_beta) is taken up at the ensemble's next
+    step, which stays bitwise equal to stepping every member alone; a member
+    cannot be freed or re-initialised while the ensemble lives (its context
+    would be left dangling), and can be once the ensemble is freed."""
     from paper_1507_02509_amd._lib import KbcError
-    sims = build(small_specs()[:2], "f32")
+    say("ensemble member beta and lifetime")
+    specs = small_specs()[:3]
+    sims, ref = build(specs, "f32"), build(specs, "f32")
     ens = Ensemble(sims)
-    with pytest.raises(KbcError, match="switched off"):
-        ens.step(2, persistent=True)
-
-
-@pytest.mark.skip(reason=PERSISTENT_OFF)
-def test_persistent_ensemble_equals_individual_steps():
-    ref = build(small_specs(), "f32")
+    ens.step(3)
     for s in ref:
-        s.step(9)
-    sims = build(small_specs(), "f32")
-    Ensemble(sims).step(4, True).step(5, True)
+        s.step(3)
+    for s in (sims[1], ref[1]):
+        s.set_beta(0.9)
+    ens.step(5)
+    for s in ref:
+        s.step(5)
     for a, b in zip(states(sims), states(ref)):
         assert torch.equal(a, b)
+    with pytest.raises(KbcError, match="live ensemble"):
+        sims[0].free()
+    ux, uy = inputs.spectral(specs[0][0], 3, 0.05, seed=1, ny=specs[0][1])
+    with pytest.raises(KbcError, match="live ensemble"):
+        sims[0].init(ux, uy)
+    ens.step(2)                       # the member context is intact
+    for s in ref:
+        s.step(2)
+    for a, b in zip(states(sims), states(ref)):
+        assert torch.equal(a, b)
+    ens.free()
+    sims[0].init(ux, uy)              # allowed again
+    sims[0].free()
 
 
-def test_uneven_ensemble_256_members():
+@pytest.mark.parametrize("form", ["f32", "f64", "f16"])
+def test_persistent_ensemble_equals_individual_steps(form):
+    """One persistent launch for all the steps (grid barrier between steps),
+    with single steps and with two fused steps per barrier, for several
+    tiles: bitwise equal to stepping every member alone; the launch reports
+    no barrier give-up."""
+    say("persistent ensemble vs individual", form)
+    ref = build(small_specs(), form)
+    for s in ref:
+        s.step(9)
+    want = states(ref)
+    configs = [((128, 2, False), (1, 0)), ((256, 1, True), (1, 0)), ((256, 1, True), (2, 8)),
+               ((256, 1, False), (2, 16))]
+    for tile, fusion in configs:
+        sims = build(small_specs(), form)
+        ens = Ensemble(sims)
+        ens.set_tile(*tile)
+        ens.set_fusion(*fusion)
+        blocks = ens.blocks
+        say("  tile", tile, "fusion", fusion, "grid", blocks)
+        assert blocks >= 8 and blocks % 8 == 0
+        ens.step(4, persistent=True).step(5, persistent=True)   # pairs; pairs and one single step
+        ens.check()
+        for a, b in zip(states(sims), want):
+            assert torch.equal(a, b), (tile, fusion)
+        assert all(s.steps == 9 for s in sims)
+        ens.free()
+
+
+def test_persistent_barrier_gives_up_and_reports():
+    """The grid barrier's wait is bounded: with a spin limit of 0 a workgroup
+    that finds the barrier still closed at its first poll gives up, every
+    wait of the launch ends at once, and lbm_ensemble_check reports
+    LBM_ESYNC (the states are invalid).  The ensemble then recovers: states
+    restored, default limit, the persistent launch equals stepping alone."""
+    from paper_1507_02509_amd._lib import KbcError
+    say("persistent barrier give-up")
+    specs = [(512, 512, 1e-4, 7)] + small_specs()[:2]
+    sims, ref = build(specs, "f32"), build(specs, "f32")
+    snaps = [s.state_buffer().clone() for s in sims]
+    ens = Ensemble(sims)
+    ens.set_spin_limit(0)
+    ens.step(12, persistent=True)
+    with pytest.raises(KbcError, match="grid barrier"):
+        ens.check()
+    ens.check()                      # the flag was cleared by the report
+    for s, snap in zip(sims, snaps):      # 12 steps: the state is back in the same buffer
+        s.state_buffer().copy_(snap)
+        s.lib.lbm_set_step(s.ctx, 0)
+    ens.set_spin_limit(1 << 22)
+    ens.step(12, persistent=True).check()
+    for s in ref:
+        s.step(12)
+    for a, b in zip(states(sims), states(ref)):
+        assert torch.equal(a, b)
+    ens.free()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_uneven_ensemble_256_members(persistent):
     """The ensemble workload: 256 members, N uniform over {128, 256, 512, 1024},
     nu log-uniform over [1e-5, 1e-3], per-member seeds; KBC-B, FP32.  50
-    batched steps (one launch per step over all members) equal per-member
+    steps (per-step launches, or one persistent launch) equal per-member
     stepping bit for bit (checked on 8 members drawn across the sizes)."""
     specs = inputs.ensemble_members(256, master_seed=4)
-    say("256-member ensemble; nodes", sum(n * n for n, _, _ in specs))
+    say("256-member ensemble; nodes", sum(n * n for n, _, _ in specs), "persistent", persistent)
     sims = make_members(specs, form="f32")
     pick = [0, 1, 2, 3, 64, 127, 200, 255]
     snaps = [sims[i].state_buffer().clone() for i in pick]
     ens = Ensemble(sims)
-    ens.step(50, persistent=False)
-    torch.cuda.synchronize()
+    ens.step(50, persistent=persistent)
+    ens.check()
     for i, snap in zip(pick, snaps):
         s = sims[i]
         ref = Sim(s.nx, s.ny, s.params.beta, variant="B", form="f32")
@@ -151,6 +222,9 @@ def test_autotuner_restores_state_and_caches(tmp_path, monkeypatch):
     ens = Ensemble(sims)
     b2, t2 = autotune.tune_ensemble(ens, steps=2, reps=1)
     assert b2 in autotune.ENSEMBLE_CANDIDATES
+    b3, t3 = autotune.tune_ensemble(ens, steps=2, reps=1, persistent=True)
+    assert b3 in autotune.ENSEMBLE_CANDIDATES and len(t3) == len(autotune.ENSEMBLE_CANDIDATES)
+    ens.check()
     ref = build(small_specs(), "f32")
     for a, b in zip(states(sims), states(ref)):
         assert torch.equal(a, b)
