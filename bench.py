@@ -5,15 +5,21 @@ Workload (the roofline run): one periodic 16384 x 16384 lattice, a seeded
 divergence-free random initial field with E(k) ~ k^4 exp(-2 (k/32)^2),
 u_rms = 0.05, rho = 1, nu = 1e-4, Grad initialisation with central
 differences; KBC model B, populations stored as FP32 deviations, FP32
-arithmetic.  One step is one fused pull-stream + collide launch over the
-whole lattice.
+arithmetic.  The library's default launch runs two fused pull-stream +
+collide steps per kernel launch (the first step's result stays in LDS), so
+the state crosses HBM once per two steps.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 prints one JSON line.  `value` is lattice updates per second (MLUPS) over the
-K timed steps; `roofline` relates the kernel's algorithmic bytes (9 loads + 9
-stores of 4 bytes per node) to the MI355X HBM peak; `cpu_baseline` times the
-FP64 CPU oracle on a bounded sample of the same workload.
+K timed steps.  `roofline` describes the dominant kernel: with two fused
+steps per launch it is bound by vector-ALU issue, so `bound` is "alu" and
+`achieved` counts the FP32 operations of its compiled collision against the
+published FP32 vector peak; the same object gives the HBM side per launch
+(72 B per node per launch over the launch time, against 8 TB/s).  With
+--fusion 1 (one step per launch) the kernel is HBM-bound and `bound` is
+"hbm".  `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the
+same workload on all host cores (up to 16) and on one core.
 """
 from __future__ import annotations
 
@@ -37,9 +43,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 _CSRC = os.path.join(ROOT, "paper_1507_02509_amd", "csrc")
 STEP_SOURCES = [os.path.join(_CSRC, f)
                 for f in ("kbc_step.hip", "kbc_step2.hip", "kbc_tile.hpp", "kbc_tile2.hpp", "kbc_device.hpp")]
-# FP arithmetic operations of one KBC-B collision per node (adds, multiplies,
-# reciprocals and conversions count one, FMAs two), counted in the gfx950 code
-# of the single-step kernel; the vector peaks are MI355X's published ones
+# Floating-point operations of one KBC-B collision per node as compiled for
+# gfx950 (adds, multiplies, reciprocals and conversions count one, FMAs two),
+# counted in the single-step kernel's code: "compiled-instruction FLOPs", not
+# a minimal operation count of the method.  The vector peaks are MI355X's
+# published ones; the FP32 one assumes packed FP32 (two lanes per
+# instruction), which this library never issues, so at most half of it is
+# attainable here.
 FLOPS_PER_NODE_STEP = {"f32": 266, "f16": 302, "f64": 382}
 VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f16": 157.3, "f64": 78.6}
 VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s: 256 CUs, 64 lanes, nominal clock
@@ -127,45 +137,66 @@ def time_adjoint(n, nu, seed, k0, dev, steps=20):
     return ms
 
 
+C5 = {"n": 512, "steps": 2000, "variant": "D", "gamma_guard": 1e-4, "nu": 1e-3, "form": "f32"}
+
+
 def time_c5(dev):
     """Forward and backward of the differentiable rollout on the adjoint
-    workload: 512^2, KBC-B FP32, 2000 steps, sqrt(N) checkpoints."""
+    workload: 512^2 decaying turbulence (k0 = 8, u_rms = 0.05, nu = 1e-3),
+    FP32, 2000 steps, sqrt(N) checkpoints, loss 1/2 |u(T) - u_t|^2.  The
+    collision is KBC-D with stabiliser guard 1e-4: the KBC configuration whose
+    2000-step gradient is verified (central finite differences of the FP64
+    forward and the FP32 vs FP64 gradient, and the FP64 discrete adjoint
+    against the oracle's over 50 steps); with KBC-B and the default guard the
+    exact gradient grows to ~1e30 over 2000 steps and carries no meaning.
+    The gradient is checked to be finite and its norm reported."""
     import torch
     from paper_1507_02509_amd import inputs
     from paper_1507_02509_amd.autograd import rollout
     from paper_1507_02509_amd.sim import beta_from_nu
-    n, nsteps = 512, 2000
+    n, nsteps = C5["n"], C5["steps"]
     ux0, uy0 = (torch.from_numpy(a).to(dev) for a in inputs.spectral(n, 8, 0.05, seed=5))
     tx, ty = (torch.from_numpy(a).to(dev) for a in inputs.spectral(n, 8, 0.03, seed=55))
     out = {}
     for rep in range(2):
         u0x = ux0.clone().requires_grad_(True)
         u0y = uy0.clone().requires_grad_(True)
-        b = torch.tensor(beta_from_nu(1e-3), dtype=torch.float64, device=dev, requires_grad=True)
+        b = torch.tensor(beta_from_nu(C5["nu"]), dtype=torch.float64, device=dev, requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, ux, uy = rollout(u0x, u0y, b, nsteps, form="f32")
+        _, ux, uy = rollout(u0x, u0y, b, nsteps, form=C5["form"], variant=C5["variant"],
+                            gamma_guard=C5["gamma_guard"])
         loss = 0.5 * (((ux - tx) ** 2).sum() + ((uy - ty) ** 2).sum())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        out = {"forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
-               "backward_over_forward": round((t2 - t1) / (t1 - t0), 3)}
+        gnorm = float(torch.sqrt((u0x.grad ** 2).sum() + (u0y.grad ** 2).sum()))
+        if not (np.isfinite(gnorm) and np.isfinite(b.grad.item())):
+            raise RuntimeError(f"non-finite rollout gradient (|grad u0| {gnorm}, dL/dbeta {b.grad.item()})")
+        out = {"config": f"KBC-{C5['variant']}, guard {C5['gamma_guard']:g}, {C5['form']}, {n}^2, {nsteps} steps",
+               "forward_s": round(t1 - t0, 4), "backward_s": round(t2 - t1, 4),
+               "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+               "grad_u0_norm": gnorm, "dL_dbeta": b.grad.item(), "loss": loss.item()}
     return out
 
 
-def time_ensemble(dev, steps=60):
-    """The uneven ensemble: 256 members, N in {128, 256, 512, 1024}, KBC-B FP32,
-    one batched launch over all members' tiles per step or per two fused
-    steps (the library's default)."""
+def time_ensemble(dev, steps=60, persistent_steps=2000):
+    """The uneven ensemble: 256 members, N in {128, 256, 512, 1024}, KBC-B FP32.
+    (a) the library's default launch (one batched launch over all members'
+    tiles per two fused steps), `steps` steps; (b) the workload as stated:
+    `persistent_steps` steps in ONE persistent launch (grid barrier between
+    pairs of steps) with the launch configuration the autotuner picks for the
+    persistent mode on this ensemble (timed on the ensemble itself, state
+    restored), checked for barrier give-ups afterwards."""
     import torch
-    from paper_1507_02509_amd import inputs
+    from paper_1507_02509_amd import autotune, inputs
     from paper_1507_02509_amd.ensemble import Ensemble, make_members
     specs = inputs.ensemble_members(256, master_seed=4)
     sims = make_members(specs, form="f32", device=dev)
     ens = Ensemble(sims)
+    nodes = ens.nodes
     ens.step(10)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -174,15 +205,30 @@ def time_ensemble(dev, steps=60):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    nodes = ens.nodes
     spl = ens.fusion
+    res = {"members": 256, "nodes": nodes, "ms_per_step": round(ms, 4),
+           "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "steps_per_launch": spl,
+           "hbm_frac": round(72 * nodes / (spl * ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "launch": "one batched launch over all members per " + ("two steps" if spl == 2 else "step")}
+    best, _ = autotune.tune_ensemble(ens, steps=10, reps=2, persistent=True, use_cache=False)
+    blocks = ens.blocks
+    ens.step(2, persistent=True)
+    torch.cuda.synchronize()
+    e0.record()
+    ens.step(persistent_steps, persistent=True)
+    e1.record()
+    torch.cuda.synchronize()
+    pms = e0.elapsed_time(e1) / persistent_steps
+    ens.check()
+    d = sims[255].diagnostics()
+    res["persistent"] = {"steps": persistent_steps, "launches": 1, "grid_workgroups": blocks,
+                         "autotuned_config": list(best), "ms_per_step": round(pms, 4),
+                         "mlups": round(nodes / (pms * 1e-3) / 1e6, 1),
+                         "member_255_nonfinite": d["n_nonfinite"]}
     ens.free()
     del ens, sims
     torch.cuda.empty_cache()
-    return {"members": 256, "nodes": nodes, "ms_per_step": round(ms, 4),
-            "mlups": round(nodes / (ms * 1e-3) / 1e6, 1), "steps_per_launch": spl,
-            "hbm_frac": round(72 * nodes / (spl * ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "launch": "one batched launch over all members per " + ("two steps" if spl == 2 else "step")}
+    return res
 
 
 def form_errors(n, nu, seed, k0, dev, steps=10):
@@ -204,23 +250,10 @@ def form_errors(n, nu, seed, k0, dev, steps=10):
     return {"steps": steps, "u_rel_err_vs_f64": res}
 
 
-def cpu_baseline(n: int, nu: float, seed: int, k0: float, target_s: float = 16.0):
-    """The FP64 oracle (unmodified) on a 2048-row slab of the same workload,
-    treated as a periodic 16384 x 2048 lattice (the same per-node work)."""
+def _oracle_mlups(p, f, target_s: float):
+    """Node updates per second of the oracle's step on state f, over about
+    target_s seconds (at least two steps)."""
     import oracle
-    from paper_1507_02509_amd import inputs
-    rows = 2048
-    try:
-        threads = len(os.sched_getaffinity(0))
-    except AttributeError:
-        threads = os.cpu_count() or 1
-    threads = max(1, min(threads, 16))
-    ux, uy = inputs.spectral(n, k0, 0.05, seed=seed, device="cuda")
-    ux = np.ascontiguousarray(ux[:rows].cpu().numpy())
-    uy = np.ascontiguousarray(uy[:rows].cpu().numpy())
-    p = oracle.Params(n, rows, 1.0 / (6.0 * nu + 1.0), collision=oracle.KBC, variant=oracle.KBC_B,
-                      threads=threads)
-    f = oracle.init(p, ux, uy)
     t0 = time.perf_counter()
     f1 = oracle.step(p, f)
     one = time.perf_counter() - t0
@@ -228,12 +261,43 @@ def cpu_baseline(n: int, nu: float, seed: int, k0: float, target_s: float = 16.0
     t0 = time.perf_counter()
     for _ in range(nsteps):
         f1 = oracle.step(p, f1)
-    dt = time.perf_counter() - t0
-    total = nsteps + 1
-    mlups = n * rows * total / (dt + one) / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"KBC-B FP64 oracle, {total} steps of a periodic {n} x {rows} slab of the "
-                      f"same seeded field ({n * rows * total / 1e6:.0f} M node updates, {dt + one:.1f} s)"}
+    dt = time.perf_counter() - t0 + one
+    return p.nx * p.ny * (nsteps + 1) / dt / 1e6, nsteps + 1, dt
+
+
+def cpu_baseline(n: int, nu: float, seed: int, k0: float):
+    """The FP64 oracle (unmodified) on slabs of the same workload, treated as
+    periodic lattices of the same row length (the same per-node work): KBC-B
+    on all host cores (up to 16) over a 2048-row slab for about 12 s, on one
+    core over a 128-row slab for about 5 s, and LBGK likewise (about 4 s and
+    3 s) for the oracle's KBC / LBGK time ratio."""
+    import oracle
+    from paper_1507_02509_amd import inputs
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    threads = max(1, min(threads, 16))
+    ux, uy = inputs.spectral(n, k0, 0.05, seed=seed, device="cuda")
+    beta = 1.0 / (6.0 * nu + 1.0)
+    res = {}
+    for rows, nt, label, tk, tl in ((2048, threads, "all", 12.0, 4.0), (128, 1, "one", 5.0, 3.0)):
+        vx = np.ascontiguousarray(ux[:rows].cpu().numpy())
+        vy = np.ascontiguousarray(uy[:rows].cpu().numpy())
+        pk = oracle.Params(n, rows, beta, collision=oracle.KBC, variant=oracle.KBC_B, threads=nt)
+        pl = oracle.Params(n, rows, beta, collision=oracle.LBGK, threads=nt)
+        f = oracle.init(pk, vx, vy)
+        res[label] = (rows, nt, _oracle_mlups(pk, f, tk), _oracle_mlups(pl, f, tl))
+    rows, nt, (k_all, steps_all, dt_all), (l_all, _, _) = res["all"]
+    rows1, _, (k_one, steps_one, dt_one), (l_one, _, _) = res["one"]
+    return {"value": round(k_all, 3), "unit": "MLUPS", "cores": nt, "kind": "oracle",
+            "sample": f"KBC-B FP64 oracle, {steps_all} steps of a periodic {n} x {rows} slab of the "
+                      f"same seeded field ({n * rows * steps_all / 1e6:.0f} M node updates, {dt_all:.1f} s); "
+                      f"one core: {steps_one} steps of a {n} x {rows1} slab ({dt_one:.1f} s); LBGK on the same "
+                      f"slabs for the ratio",
+            "one_core": {"value": round(k_one, 3), "unit": "MLUPS", "cores": 1},
+            "lbgk": {"value": round(l_all, 3), "one_core_value": round(l_one, 3), "unit": "MLUPS"},
+            "kbc_over_lbgk_time": {"all_cores": round(l_all / k_all, 3), "one_core": round(l_one / k_one, 3)}}
 
 
 def main():
@@ -295,11 +359,15 @@ def main():
         peak = VECTOR_PEAK_TFLOPS[args.form]
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                     "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kname,
+                    "flops_kind": "FP32 operations of the compiled collision per node-step "
+                                  f"({FLOPS_PER_NODE_STEP[args.form]}; FMA = 2), x {spl} steps x nodes per launch",
+                    "peak_kind": "published FP32 vector peak, which assumes packed FP32; this library issues "
+                                 "no packed FP32, so non-packed issue reaches at most half of it",
                     "steps_per_launch": spl, "algorithmic_flops_per_launch": flops_launch,
-                    "algorithmic_bytes_per_launch": bytes_launch, "hbm_GBs": round(hbm_gbs, 1),
-                    "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
-                    "single_pass_hbm_frac": round(BYTES_PER_NODE[args.form] * nodes / (ms * 1e-3) / 1e9
-                                                  / HBM_PEAK_GBS, 4)}
+                    "algorithmic_bytes_per_launch": bytes_launch,
+                    # the HBM side of the same launch: the state read and written once per launch
+                    "hbm_GBs_per_launch": round(hbm_gbs, 1),
+                    "hbm_frac_per_launch": round(hbm_gbs / HBM_PEAK_GBS, 4)}
         # the kernel's own limit: vector instructions issued (counted by the
         # profiler per node-step) against one instruction per lane and clock
         # on 256 CUs x 64 lanes at the nominal 2.4 GHz (packed FP32 is not

@@ -12,6 +12,7 @@ import torch
 from paper_1507_02509_amd import inputs
 from paper_1507_02509_amd.autograd import rollout
 from paper_1507_02509_amd.sim import Sim, beta_from_nu
+from oracle_sensitivity import K_SENS, SEEDS, perturbed
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +45,34 @@ def random_state(orc, nx, ny, beta, seed, eps=2e-3):
 
 def field_err(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+EPS32 = 2.0 ** -24
+
+
+def f32_adjoint_bars(orc, p, f, lam_next):
+    """Bars of an FP32 adjoint step against the FP64 oracle's at the stored
+    state f (max |diff| / max |oracle| for lambda, relative for the summed
+    dL/dbeta), from the oracle alone: the kernel computes in binary32, so
+    its lambda moves at least as much as the oracle's does when the stored
+    deviations g = f - W are perturbed by one binary32 rounding,
+    g (1 + 2^-24 xi) (largest of three seeds, s_lam and s_beta); the bar is
+    K_SENS times that, but not below 16 binary32 units for lambda (the
+    arithmetic of an O(1) adjoint field) and 4 kappa binary32 units for
+    dL/dbeta, kappa = sum |dbeta_x| / |sum dbeta_x| being the condition number
+    of the sum of per-node terms each formed in binary32.  Model C's
+    <dh|dh> holds only third- and fourth-order moments, so the 1/<dh|dh> in
+    the derivative of gamma* makes its s_lam about 20 times B's."""
+    lo, db = orc.adjoint_step(p, f, lam_next)
+    W = orc.weights()[:, None, None]
+    s_lam = s_beta = 0.0
+    for seed in SEEDS:
+        xi = np.random.default_rng(seed).standard_normal(f.shape)
+        lp, dbp = orc.adjoint_step(p, W + (f - W) * (1.0 + EPS32 * xi), lam_next)
+        s_lam = max(s_lam, field_err(lp, lo))
+        s_beta = max(s_beta, abs(dbp.sum() - db.sum()) / abs(db.sum()))
+    kappa = np.abs(db).sum() / abs(db.sum())
+    return lo, db, max(16 * EPS32, K_SENS * s_lam), max(4 * kappa * EPS32, K_SENS * s_beta)
 
 
 def to_lam(sim, lam_np):
@@ -90,13 +119,12 @@ def test_adjoint_step_parity_f32(orc, coll, var):
     lout = s.new_adjoint()
     acc = torch.zeros(1, dtype=torch.float64, device="cuda")
     s.adjoint_step(s.state_buffer(), to_lam(s, lam_next), lout, acc)
-    lo, dbo = orc.adjoint_step(oparams(orc, nx, ny, beta, coll, var), f0r, lam_next)
+    lo, dbo, bar, bar_b = f32_adjoint_bars(orc, oparams(orc, nx, ny, beta, coll, var), f0r, lam_next)
     err = field_err(s.planes(lout).cpu().numpy(), lo)
-    say("  f32 lam err", err, "dbeta", acc.item(), dbo.sum())
-    # FP32 bound: the derivative of gamma* carries 1 / <dh|dh>, which
-    # amplifies the binary32 rounding of the state
-    assert err < 1e-3
-    assert acc.item() == pytest.approx(dbo.sum(), rel=1e-3)
+    eb = abs(acc.item() - dbo.sum()) / abs(dbo.sum())
+    say(f"  f32 lam err {err:.3e} (bar {bar:.3e}), dbeta err {eb:.3e} (bar {bar_b:.3e})")
+    assert err < bar and bar <= 2e-3
+    assert eb < bar_b
 
 
 @pytest.mark.parametrize("coll,var", [("lbgk", "A"), ("kbc", "B")])
@@ -104,7 +132,7 @@ def test_adjoint_step_parity_f16(orc, coll, var):
     """The adjoint step of the FP16 storage form (FP32 arithmetic) from the
     oracle's binary16 rounding of the state, which the form decodes exactly:
     what separates it from the FP64 oracle adjoint at that state is FP32
-    arithmetic alone, so the FP32 bars apply."""
+    arithmetic alone, so the FP32 bars (f32_adjoint_bars) apply."""
     nx, ny = 67, 45
     say("adjoint step f16", coll, var)
     beta = beta_from_nu(1e-3)
@@ -118,11 +146,12 @@ def test_adjoint_step_parity_f16(orc, coll, var):
     lout = s.new_adjoint()
     acc = torch.zeros(1, dtype=torch.float64, device="cuda")
     s.adjoint_step(s.state_buffer(), to_lam(s, lam_next), lout, acc)
-    lo, dbo = orc.adjoint_step(oparams(orc, nx, ny, beta, coll, var), f0r, lam_next)
+    lo, dbo, bar, bar_b = f32_adjoint_bars(orc, oparams(orc, nx, ny, beta, coll, var), f0r, lam_next)
     err = field_err(s.planes(lout).cpu().numpy(), lo)
-    say("  f16 lam err", err, "dbeta", acc.item(), dbo.sum())
-    assert err < 1e-3
-    assert acc.item() == pytest.approx(dbo.sum(), rel=1e-3)
+    eb = abs(acc.item() - dbo.sum()) / abs(dbo.sum())
+    say(f"  f16 lam err {err:.3e} (bar {bar:.3e}), dbeta err {eb:.3e} (bar {bar_b:.3e})")
+    assert err < bar and bar <= 2e-3
+    assert eb < bar_b
 
 
 @pytest.mark.parametrize("mode", ["eq", "grad_cd"])
@@ -316,19 +345,33 @@ def test_turbulence_512_gradient(coll, var, nsteps, guard, h, fd_tol, f32_tol):
     assert b32 == pytest.approx(b64, rel=f32_tol)
 
 
-def test_turbulence_512_adjoint_matches_oracle(orc):
-    """Full 512^2 lattice against the FP64 CPU adjoint (complex-step Jacobians
-    of the oracle's collision), over 3 steps of KBC-B in FP64."""
+@pytest.mark.parametrize("var,guard", [("B", 1e-12), ("D", 1e-4)])
+def test_turbulence_512_adjoint_matches_oracle(orc, var, guard):
+    """Full 512^2 lattice against the FP64 CPU discrete adjoint (complex-step
+    Jacobians of the oracle's collision) over 50 steps in FP64: KBC-B with the
+    default guard, and KBC-D with guard 1e-4, the configuration whose
+    2000-step gradient the benchmark times.  dL/dbeta to 1e-10 relative; the
+    gradient w.r.t. the initial velocity (max |diff| / max |oracle|) to
+    max(1e-10, 5 s), s being how far the oracle's own gradient moves when
+    its initial velocity is perturbed by 1e-15 relative (one seed: each
+    oracle gradient takes tens of seconds): over 50 steps the derivative of
+    gamma* carries rounding differences of the trajectory to about 1e-9."""
     n, ux0, uy0, tx, ty, _, _ = c5_setup()
-    say("512 adjoint vs oracle")
-    beta, nsteps = beta_from_nu(1e-3), 3
-    g64, b64 = c5_grad("f64", nsteps, ux0, uy0, tx, ty)
-    ogx, ogy, odb = oracle_gradient(orc, oparams(orc, n, n, beta, "kbc", "B"), ux0, uy0,
-                                    tx.cpu().numpy(), ty.cpu().numpy(), nsteps)
+    say("512 adjoint vs oracle", var, guard)
+    beta, nsteps = beta_from_nu(1e-3), 50
+    g64, b64 = c5_grad("f64", nsteps, ux0, uy0, tx, ty, variant=var, gamma_guard=guard)
+    p = oparams(orc, n, n, beta, "kbc", var)
+    p.gamma_guard = guard
+    p.threads = 16
+    txn, tyn = tx.cpu().numpy(), ty.cpu().numpy()
+    ogx, ogy, odb = oracle_gradient(orc, p, ux0, uy0, txn, tyn, nsteps)
     og = np.concatenate([ogx.ravel(), ogy.ravel()])
     err = float(np.abs(g64.cpu().numpy() - og).max() / np.abs(og).max())
-    say("  grad err", err, "beta", b64, odb)
-    assert err < 1e-10
+    px, py, _ = oracle_gradient(orc, p, perturbed(ux0, 0), perturbed(uy0, 0), txn, tyn, nsteps)
+    sens = float(np.abs(np.concatenate([px.ravel(), py.ravel()]) - og).max() / np.abs(og).max())
+    bar = max(1e-10, K_SENS * sens)
+    say(f"  grad err {err:.3e}, oracle self-sensitivity {sens:.3e}, bar {bar:.3e}; dL/dbeta {b64!r} vs {odb!r}")
+    assert err < bar
     assert b64 == pytest.approx(odb, rel=1e-10)
 
 
@@ -359,7 +402,8 @@ def test_adjoint_step_parity_exact_stabilizer(orc, form, var):
     (result1), differentiated by the implicit function theorem on the GPU)
     against the oracle's complex-step adjoint through its own Newton
     iteration.  FP64 bar 1e-10 (both roots are solved to 1e-15 relative; the
-    derivative carries 1 / F'(gamma)); FP32 bar 1e-3 as for the estimate."""
+    derivative carries 1 / F'(gamma)); FP32 bars as for the estimate
+    (f32_adjoint_bars)."""
     nx, ny = 67, 45
     say("adjoint step exact", form, var)
     beta = beta_from_nu(1e-3)
@@ -386,8 +430,11 @@ def test_adjoint_step_parity_exact_stabilizer(orc, form, var):
         assert err < 1e-10
         assert acc.item() == pytest.approx(dbo.sum(), rel=1e-8, abs=1e-12)
     else:
-        assert err < 1e-3
-        assert acc.item() == pytest.approx(dbo.sum(), rel=1e-3)
+        _, _, bar, bar_b = f32_adjoint_bars(orc, oparams_exact(orc, nx, ny, beta, var), f0, lam_next)
+        eb = abs(acc.item() - dbo.sum()) / abs(dbo.sum())
+        say(f"  bars: lam {bar:.3e}, dbeta {bar_b:.3e} (dbeta err {eb:.3e})")
+        assert err < bar and bar <= 2e-3
+        assert eb < bar_b
 
 
 def test_rollout_gradient_exact_stabilizer_matches_oracle_f64(orc):
@@ -438,8 +485,8 @@ def test_adjoint_two_rows_per_thread_f32(orc):
     lo, dbo = orc.adjoint_step(p, f0r, lam_next)
     err = field_err(lg, lo)
     say(f"  lam err {err:.3e}, dbeta {acc.item():.9e} {dbo.sum():.9e}")
-    assert err < 1e-3
-    assert acc.item() == pytest.approx(dbo.sum(), rel=1e-3)
+    assert err < 1e-4
+    assert acc.item() == pytest.approx(dbo.sum(), rel=1e-4)
     ux0, uy0 = inputs.spectral(nx, 3, 0.05, seed=66, ny=ny)
     grads = []
     for overlap in (False, True):
