@@ -279,6 +279,26 @@ int lbm_adjoint_seed(lbm_ctx* c, const void* state, const double* dL_drho, const
  * lam_out = dL/df^n and adds the step's dL/dbeta to *dbeta. */
 int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta);
 
+/* lbm_adjoint_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, kernels and results, bit for bit, but the step's
+ * per-workgroup dL/dbeta partials live in a fixed device array of
+ * LBM_NOALLOC_SCRATCH_DOUBLES doubles (8 MiB; one per GPU the library runs
+ * on, held until the process ends) instead of scratch the context allocates,
+ * and the call allocates nothing (no hipMalloc, hipFree or allocating
+ * library call).  Limit: the step needs adjoint partials plus one slice of
+ * doubles, about one per 512 nodes for FP32/FP16 lattices of at least 8192
+ * tiles of 128 x 4 (so up to about 5.3e8 nodes, e.g. 16384 x 32768) and one
+ * per 256 nodes otherwise (FP64 up to just under 16384 x 16384); larger
+ * lattices return LBM_EINVAL before any launch.  Every call on one GPU shares
+ * that GPU's array and leaves its contents behind: nothing in it needs to
+ * start at zero (a call writes every value before reading it), but calls
+ * that overlap on one GPU (two streams, two host threads) race on it.  The
+ * context's device must be current (LBM_EINVAL otherwise); the array's
+ * address is looked up on the first call on each device. */
+#define LBM_NOALLOC_SCRATCH_DOUBLES (1 << 20)
+int lbm_adjoint_step_noalloc(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta);
+
 /* One checkpoint segment of the backward pass: from state0 = f^s, recompute
  * f^{s+1} .. f^{s+k-1} into slots[0 .. k-2] (population buffers of this
  * context's layout), then run k adjoint steps from lam_in = dL/df^{s+k} down

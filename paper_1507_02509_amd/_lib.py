@@ -81,6 +81,7 @@ _SIGS = {
     "lbm_ensemble_blocks": (_c.c_int, [_vp]),
     "lbm_ensemble_set_spin_limit": (_c.c_int, [_vp, _c.c_uint32]),
     "lbm_ensemble_check": (_c.c_int, [_vp]),
+    "lbm_adjoint_step_noalloc": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_ensemble_free": (_c.c_int, [_vp]),
     "lbm_set_adjoint_gamma": (_c.c_int, [_vp, _c.c_int32]),
     "lbm_adjoint_bytes": (_c.c_size_t, [_c.c_int32, _c.c_int32, _c.c_int32]),

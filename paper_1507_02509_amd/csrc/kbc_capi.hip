@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,6 +39,7 @@ struct lbm_ctx {
     int ens_refs;           // live ensembles holding this context (lbm_free refuses while > 0)
     uint64_t gen;           // parameter generation: bumped when beta changes, so that an
                             // ensemble holding the context rebuilds its member table
+    int device;             // HIP device current at lbm_init
 };
 
 namespace {
@@ -184,6 +186,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     c->gnext[1] = 1;
     c->ens_refs = 0;
     c->gen = 0;
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
     rc = kbc::launch_init(c->L, buf_a, rho, ux, uy, grad, mode);
     if (rc) {
         delete c;
@@ -536,6 +539,65 @@ int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* la
     if (rc) return rc;
     return launch_result(kbc::launch_adjoint_step(c->L, state, lam_in, lam_out, c->ascratch, c->ascratch + nb, dbeta),
                          "lbm_adjoint_step");
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of lbm_adjoint_step_noalloc: a fixed device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never uses the
+// name itself (on the host it is only a stand-in for the symbol): the
+// device's address comes from hipGetSymbolAddress, looked up once per device.
+static __device__ __align__(256) double scratch[LBM_NOALLOC_SCRATCH_DOUBLES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// This device's address of `scratch` (the device must be current), or NULL
+// with the error set.
+double* noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        fail(LBM_EINVAL, "device %d out of the supported range", dev);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "lbm_adjoint_step_noalloc scratch address");
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_adjoint_step_noalloc(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta) {
+    if (!c || !state || !lam_in || !lam_out || lam_in == lam_out)
+        return fail(LBM_EINVAL, "ctx, state and two distinct adjoint buffers are required");
+    const int64_t nb = kbc::adjoint_partials(c->L), ng = kbc::adjoint_slice_len(c->L);
+    if (nb + ng > static_cast<int64_t>(LBM_NOALLOC_SCRATCH_DOUBLES))
+        return fail(LBM_EINVAL,
+                    "lbm_adjoint_step_noalloc: this %d x %d lattice needs %lld doubles of scratch, above the "
+                    "fixed %d (use lbm_adjoint_step)",
+                    c->p.nx, c->p.ny, static_cast<long long>(nb + ng), LBM_NOALLOC_SCRATCH_DOUBLES);
+    int dev = -1;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "lbm_adjoint_step_noalloc");
+    if (dev != c->device)
+        return fail(LBM_EINVAL, "lbm_adjoint_step_noalloc: device %d is current, the context's is %d", dev,
+                    c->device);
+    double* p = noalloc_scratch(dev);
+    if (!p) return LBM_EHIP;
+    return launch_result(kbc::launch_adjoint_step(c->L, state, lam_in, lam_out, p, p + nb, dbeta),
+                         "lbm_adjoint_step_noalloc");
 }
 
 int lbm_adjoint_segment(lbm_ctx* c, const void* state0, void* const* slots, int32_t k, void* lam_in,

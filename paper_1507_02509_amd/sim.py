@@ -224,6 +224,13 @@ class Sim:
         L.check(self.lib.lbm_adjoint_step(self.ctx, L.ptr(state), L.ptr(lam_in), L.ptr(lam_out), L.ptr(dbeta)),
                 "lbm_adjoint_step")
 
+    def adjoint_step_noalloc(self, state, lam_in, lam_out, dbeta=None):
+        """lbm_adjoint_step_noalloc: the same step with the library's fixed
+        per-GPU scratch array (allocates nothing; overlapping calls on one
+        GPU race)."""
+        L.check(self.lib.lbm_adjoint_step_noalloc(self.ctx, L.ptr(state), L.ptr(lam_in), L.ptr(lam_out),
+                                                  L.ptr(dbeta)), "lbm_adjoint_step_noalloc")
+
     def adjoint_segment(self, state0, slots, k: int, lam_in, lam_out, dbeta=None) -> int:
         """Recompute and back-propagate one checkpoint segment (see
         lbm_adjoint_segment); returns 0 if the result is in lam_in, 1 if in lam_out."""
