@@ -208,22 +208,41 @@ def test_step_parity_f32(orc, coll, var):
     assert errs[0] < 2e-5 and errs[1] < 1e-4
 
 
-@pytest.mark.parametrize("coll,var", [("lbgk", "A"), ("kbc", "B")])
+@pytest.mark.parametrize("coll,var", CASES)
 def test_step_parity_f16(orc, coll, var):
+    """FP16 deviation storage (FP32 arithmetic), every collision, after 1 and
+    10 steps, per field: each population plane, rho, u_x, u_y.  Against the
+    oracle run with the same binary16 storage rounding after every step (the
+    FP64 arithmetic then differs from the kernel's FP32 only where FP32
+    rounding flips a binary16 rounding of a stored value, a change of about
+    5e-4 of its plane's largest deviation), bars 2e-3 after one step and
+    5e-3 after ten (populations and velocity; the density's deviation from
+    1 is printed); and against the plain FP64 oracle, which states the form's
+    own error (printed)."""
     nx, ny = 67, 45
     say("f16 step parity", coll, var)
     beta = beta_from_nu(1e-3)
     f0 = random_state(orc, nx, ny, beta, seed=13, eps=1e-3)
-    s = Sim(nx, ny, beta, collision=coll, variant=var, form="f16")
-    s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
     p = orc_params(orc, nx, ny, beta, coll, var)
     f0r = orc.round_storage(p, f0, "f16")
-    s.set_populations(f0)
-    assert pop_err(s.get_populations().cpu().numpy(), f0r) < 1e-12
-    s.step(1)
-    err = pop_err(s.get_populations().cpu().numpy(), orc.run(p, f0r, 1))
-    say("  f16 error", err)
-    assert err < 5e-3
+    for nsteps, bar in ((1, 2e-3), (10, 5e-3)):
+        s = Sim(nx, ny, beta, collision=coll, variant=var, form="f16")
+        s.init(np.zeros((ny, nx)), np.zeros((ny, nx)), mode="eq")
+        s.set_populations(f0)
+        assert pop_err(s.get_populations().cpu().numpy(), f0r) < 1e-12
+        s.step(nsteps)
+        fg = s.get_populations().cpu().numpy()
+        rho, vx, vy = (t.cpu().numpy() for t in s.moments())
+        fst = orc.run(p, f0r, nsteps, storage="f16")
+        fo = orc.run(p, f0, nsteps)
+        errs = {}
+        for name, ref in (("stored", fst), ("fp64", fo)):
+            orho, ox, oy = orc.moments(p, ref)
+            errs[name] = (pop_err(fg, ref), field_err(rho - 1.0, orho - 1.0), field_err(vx, ox), field_err(vy, oy))
+        say(f"  f16 after {nsteps} steps (pop, rho - 1, ux, uy): vs stored-rounding oracle {errs['stored']}, "
+            f"vs FP64 oracle {errs['fp64']}")
+        e = errs["stored"]
+        assert max(e[0], e[2], e[3]) < bar     # rho - 1 is printed: its scale is the tiny mass deviation
 
 
 # --------------------------------------------------------------- invariants

@@ -163,3 +163,47 @@ def test_c2_long_run_all_models():
             assert de <= 1e-3 and dz <= 1e-2
             assert abs(g - 1.0) < 0.1
         say(msg)
+
+
+def test_c4_2000_steps_one_persistent_launch(orc):
+    """The ensemble workload as stated: 256 members (N in {128, 256, 512,
+    1024}, nu log-uniform in [1e-5, 1e-3], per-member seeds), KBC-B FP32,
+    2000 steps in ONE persistent launch (pairs of fused steps, grid barrier
+    between pairs).  (a) No barrier gave up, and four members, one of each
+    size, equal the same members stepped alone, bit for bit.  (b) The most
+    viscous 128^2 member (nu = 9.7e-4) against the oracle run with the same
+    binary32 storage rounding after every step: velocity field within
+    max(1e-4, 5 s), s being how far that rounding alone moves the FP64
+    oracle after 2000 steps (measured from the oracle)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1507_02509_amd.ensemble import make_members
+    specs = inputs.ensemble_members(256, master_seed=4)
+    pick = [next(i for i, m in enumerate(specs) if m[0] == n) for n in (128, 256, 512, 1024)]
+    visc = max((m[1], i) for i, m in enumerate(specs) if m[0] == 128)[1]
+    sims = make_members(specs, form="f32")
+    snaps = {i: sims[i].state_buffer().clone() for i in pick + [visc]}
+    ens = Ensemble(sims)
+    ens.step(2000, persistent=True)
+    ens.check()
+    for i in pick:
+        s = sims[i]
+        ref = Sim(s.nx, s.ny, s.params.beta, variant="B", form="f32")
+        ref.init(np.zeros((s.ny, s.nx)), np.zeros((s.ny, s.nx)), mode="eq")
+        ref.state_buffer().copy_(snaps[i])
+        ref.step(2000)
+        assert torch.equal(ref.planes(ref.state_buffer()), s.planes(s.state_buffer())), i
+    n, nu, seed = specs[visc]
+    ux, uy = inputs.spectral(n, 8, 0.05, seed=seed)
+    p = orc.Params(n, n, beta_from_nu(nu), collision=orc.KBC, variant=orc.KBC_B, threads=16)
+    f0 = orc.init(p, ux, uy)
+    _, ox, oy = orc.moments(p, orc.run(p, f0, 2000))
+    _, sx, sy = orc.moments(p, orc.run(p, orc.round_storage(p, f0, "f32"), 2000, storage="f32"))
+    _, gx, gy = (t.cpu().numpy() for t in sims[visc].moments())
+    sens = max(field_err(sx, ox), field_err(sy, oy))
+    err = max(field_err(gx, sx), field_err(gy, sy))
+    bar = max(1e-4, K_SENS * sens)
+    say(f"  c4 2000 steps, member {visc} (n={n}, nu={nu:.2e}): u err vs storage-rounded oracle {err:.3e}, "
+        f"storage sensitivity {sens:.3e}, bar {bar:.3e}")
+    assert err < bar
+    ens.free()
