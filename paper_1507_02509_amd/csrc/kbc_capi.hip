@@ -924,11 +924,11 @@ int lbm_ensemble_check(lbm_ens* e) {
     hipError_t err = hipStreamSynchronize(e->L.stream);
     if (err != hipSuccess) return hip_fail(err, "lbm_ensemble_check sync");
     uint32_t failed = 0;
-    err = hipMemcpy(&failed, &e->dsync->failed, sizeof failed, hipMemcpyDeviceToHost);
+    err = hipMemcpy(&failed, &e->dsync->failed.v, sizeof failed, hipMemcpyDeviceToHost);
     if (err != hipSuccess) return hip_fail(err, "lbm_ensemble_check read");
     if (!failed) return LBM_OK;
     const uint32_t zero = 0;
-    err = hipMemcpy(&e->dsync->failed, &zero, sizeof zero, hipMemcpyHostToDevice);
+    err = hipMemcpy(&e->dsync->failed.v, &zero, sizeof zero, hipMemcpyHostToDevice);
     if (err != hipSuccess) return hip_fail(err, "lbm_ensemble_check clear");
     return fail(LBM_ESYNC,
                 "a persistent ensemble launch gave up at a grid barrier (not every workgroup was resident "

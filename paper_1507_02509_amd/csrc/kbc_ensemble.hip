@@ -20,9 +20,9 @@
 // All of them run the per-node code of the single-lattice step on the same
 // tiles, so results are bitwise identical to stepping each member alone.
 //
-// The grid barrier (grid_barrier) is an arrival counter in device memory: a
-// workgroup finishing step s adds one and waits until the counter reaches
-// (s + 1) x (grid size).  That wait ends only if every workgroup of the grid is
+// The grid barrier (grid_barrier) counts arrivals in device memory: a
+// workgroup finishing a step counts itself in and waits until every workgroup
+// of the grid has.  That wait ends only if every workgroup of the grid is
 // resident at the same time, so the grid is capped at the resident capacity
 // computed from both the runtime's occupancy figure and the kernel's own LDS
 // and register use (resident_blocks).  As a safeguard the wait is bounded: a
@@ -52,44 +52,56 @@ __device__ __forceinline__ Coef<R> coef_of(const EnsEntry& e) {
     return K;
 }
 
-// Barrier over the whole grid of a persistent launch, the `target`-th
-// arrival of every workgroup ending it (target = (s + 1) x grid size after
-// step s).  Memory order: every wave first waits until its own stores of the
-// step have completed (they are then in the L2 of its XCD); after a workgroup
-// barrier one thread makes them visible at device scope (release fence: the
-// L2 is written back), counts the workgroup in and polls the counter with
-// device-scope atomics, then drops cached lines that another XCD may have
-// rewritten (acquire fence: the CU's L1 and the non-coherent L2 lines are
-// invalidated) before the workgroup goes on.  One write-back and one
-// invalidation per workgroup, not per wave: each acts on a whole cache.
-__device__ __forceinline__ void grid_barrier(EnsSync* sy, uint32_t target, uint32_t spin_limit) {
+// Barrier number `b` (1, 2, ...) over the whole grid of a persistent launch.
+// Arrival is counted in two levels so that no single counter takes every
+// workgroup's atomic: workgroup j of XCD band x adds one to group[x]; the
+// last of the band's m workgroups to arrive at barrier b (it reads b m - 1)
+// adds one to `count`; everyone waits until `count` reaches 8 b.
+// Memory order: every wave first waits until its own stores of the step have
+// completed (they are then in the L2 of its XCD); after a workgroup barrier
+// one thread makes them visible at device scope (release fence: the L2 is
+// written back) and counts the workgroup in; the last arriver of a band
+// first acquires what the band released and releases it on with its count
+// (acquire-release fence); after the wait, the thread drops cached lines that
+// another XCD may have rewritten (acquire fence: the CU's L1 and the
+// non-coherent L2 lines are invalidated) before the workgroup goes on.  One
+// write-back and one invalidation per workgroup, not per wave: each acts on a
+// whole cache.  Counters are read and written with device-scope atomics.
+__device__ __forceinline__ void grid_barrier(EnsSync* sy, uint32_t b, uint32_t spin_limit) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(&sy->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t m = gridDim.x >> 3;
+        const uint32_t old = __hip_atomic_fetch_add(&sy->group[blockIdx.x & 7u].v, 1u, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == b * m) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_fetch_add(&sy->count.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint32_t target = 8u * b;
         for (uint32_t it = 0;; ++it) {
-            if (__hip_atomic_load(&sy->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-            if (__hip_atomic_load(&sy->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+            if (__hip_atomic_load(&sy->count.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+            if (__hip_atomic_load(&sy->abort.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
             if (it >= spin_limit) {
-                __hip_atomic_store(&sy->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&sy->failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&sy->abort.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&sy->failed.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(8);
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
 
-// Clears the arrival counter and the give-up flag before a persistent launch
-// (the sticky `failed` word is left for the host).
+// Clears the group counters, the arrival count and the give-up flag before a
+// persistent launch (the sticky `failed` word is left for the host).
 __global__ void k_sync_reset(EnsSync* sy) {
-    if (threadIdx.x == 0) {
-        sy->count = 0u;
-        sy->abort = 0u;
-    }
+    const unsigned t = threadIdx.x;
+    if (t < 8) sy->group[t].v = 0u;
+    if (t == 8) sy->count.v = 0u;
+    if (t == 9) sy->abort.v = 0u;
 }
 
 template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
@@ -153,7 +165,7 @@ __global__ __launch_bounds__(256) void k_ens_persist(const EnsEntry* __restrict_
                                                          static_cast<S*>(e.buf[par ^ 1]), e.nx, e.ny, e.pitch,
                                                          lt % e.ntx, lt / e.ntx, coef_of<R>(e));
         }
-        if (s + 1 < nsteps) grid_barrier(sync, static_cast<uint32_t>(s + 1) * gridDim.x, spin_limit);
+        if (s + 1 < nsteps) grid_barrier(sync, static_cast<uint32_t>(s + 1), spin_limit);
     }
 }
 
@@ -182,7 +194,7 @@ __global__ __launch_bounds__(256) void k_ens2_persist(const EnsEntry* __restrict
                                                     (lt % e.ntx) * 64, (lt / e.ntx) * TH, coef_of<R>(e));
             __syncthreads();
         }
-        if (s + 1 < npairs) grid_barrier(sync, static_cast<uint32_t>(s + 1) * gridDim.x, spin_limit);
+        if (s + 1 < npairs) grid_barrier(sync, static_cast<uint32_t>(s + 1), spin_limit);
     }
 }
 

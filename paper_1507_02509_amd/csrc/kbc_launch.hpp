@@ -57,17 +57,20 @@ struct EnsEntry {
     double beta, inv_beta, two_m_inv_beta, rho0, guard, gamma_fixed;
 };
 // Grid-barrier state of a persistent ensemble launch (device memory owned by
-// the ensemble): the arrival counter and this launch's give-up flag are reset
-// by a small kernel before every persistent launch; `failed` is sticky until
-// the host reads it (lbm_ensemble_check).  Each word has a 128-byte line of
-// its own.
+// the ensemble): eight group arrival counters (one per XCD band of
+// workgroups), the count of groups that have arrived, and this launch's
+// give-up flag are reset by a small kernel before every persistent launch;
+// `failed` is sticky until the host reads it (lbm_ensemble_check).  Each word
+// has a 128-byte line of its own.
 struct EnsSync {
-    uint32_t count;
-    uint32_t pad0[31];
-    uint32_t abort;
-    uint32_t pad1[31];
-    uint32_t failed;
-    uint32_t pad2[31];
+    struct Line {
+        uint32_t v;
+        uint32_t pad[31];
+    };
+    Line group[8];
+    Line count;
+    Line abort;
+    Line failed;
 };
 struct EnsLaunch {
     const EnsEntry* table;  // device copy of the member table
