@@ -15,8 +15,9 @@
 //   * k_ens2: one launch per two fused steps, one workgroup per 64 x TH output
 //     tile (tile body of the single-lattice fused kernel, kbc_tile2.hpp);
 //   * k_ens_persist / k_ens2_persist: ONE launch for many steps (or pairs of
-//     steps): as many workgroups as the GPU holds at once, each looping over
-//     its share of the tiles every step, with a grid barrier between steps.
+//     steps): as many workgroups as the GPU holds at once, each taking tiles
+//     of its XCD's band as it asks for them (BandTiles), with a grid barrier
+//     between steps.
 // All of them run the per-node code of the single-lattice step on the same
 // tiles, so results are bitwise identical to stepping each member alone.
 //
@@ -102,6 +103,33 @@ __global__ void k_sync_reset(EnsSync* sy) {
     if (t < 8) sy->group[t].v = 0u;
     if (t == 8) sy->count.v = 0u;
     if (t == 9) sy->abort.v = 0u;
+    if (t >= 16 && t < 24) sy->claim[t - 16].v = 0u;
+}
+
+// Tiles of a persistent launch are handed out per band as the workgroups ask
+// for them: claim index k of band x is tile start + k mod B of step k / B
+// (B tiles in the band), from one counter per band that runs through all the
+// launch's steps.  A workgroup asks for its next tile as it starts one (the
+// counter's round trip overlaps the tile's first loads) and ends a step
+// holding one claim of the next step; every index below steps x B is taken
+// by exactly one workgroup.  The claimed index passes through LDS, double
+// buffered so that a value is overwritten only after every wave has read it.
+struct BandTiles {
+    int start, B;
+    uint32_t* ctr;
+};
+__device__ __forceinline__ BandTiles band_tiles(EnsSync* sy, int ntiles) {
+    const int x = static_cast<int>(blockIdx.x & 7u);
+    const int band = (ntiles + 7) >> 3;
+    BandTiles bt;
+    bt.start = x * band;
+    const int end = (bt.start + band < ntiles) ? bt.start + band : ntiles;
+    bt.B = end > bt.start ? end - bt.start : 0;
+    bt.ctr = &sy->claim[x].v;
+    return bt;
+}
+__device__ __forceinline__ int claim_tile(const BandTiles& bt) {
+    return static_cast<int>(__hip_atomic_fetch_add(bt.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
 template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
@@ -142,8 +170,7 @@ __global__ __launch_bounds__(256) void k_ens2(const EnsEntry* __restrict__ tab,
                                             coef_of<R>(e));
 }
 
-// Persistent single steps: workgroup j of XCD x takes tiles x band + j,
-// x band + j + m, ... (m workgroups per XCD) of every step.
+// Persistent single steps over the band tiles (BandTiles).
 template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_ens_persist(const EnsEntry* __restrict__ tab,
                                                      const int32_t* __restrict__ tile_member, int ntiles,
@@ -151,27 +178,35 @@ __global__ __launch_bounds__(256) void k_ens_persist(const EnsEntry* __restrict_
     using F = Form<FORM>;
     using S = typename F::S;
     using R = typename F::R;
-    const int xcd = static_cast<int>(blockIdx.x & 7u), j = static_cast<int>(blockIdx.x >> 3);
-    const int m = static_cast<int>(gridDim.x >> 3);
-    const int band = (ntiles + 7) >> 3;
-    const int start = xcd * band;
-    const int end = (start + band < ntiles) ? start + band : ntiles;
+    __shared__ int s_claim[2];
+    const BandTiles bt = band_tiles(sync, ntiles);
+    if (threadIdx.x == 0) s_claim[0] = claim_tile(bt);
+    __syncthreads();
+    int k = s_claim[0], p = 0;
     for (int s = 0; s < nsteps; ++s) {
         const int par = (parity + s) & 1;
-        for (int t = start + j; t < end; t += m) {
+        const int base = s * bt.B;
+        while (k < base + bt.B) {
+            p ^= 1;
+            int next = 0;
+            if (threadIdx.x == 0) next = claim_tile(bt);
+            const int t = bt.start + (k - base);
             const EnsEntry& e = tab[tile_member[t]];
             const int lt = t - e.tile_start;
             step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT>(static_cast<const S*>(e.buf[par]),
                                                          static_cast<S*>(e.buf[par ^ 1]), e.nx, e.ny, e.pitch,
                                                          lt % e.ntx, lt / e.ntx, coef_of<R>(e));
+            if (threadIdx.x == 0) s_claim[p] = next;
+            __syncthreads();
+            k = s_claim[p];
         }
         if (s + 1 < nsteps) grid_barrier(sync, static_cast<uint32_t>(s + 1), spin_limit);
     }
 }
 
-// Persistent pairs of fused steps; the tile body holds a workgroup barrier
-// and reuses the LDS windows, so consecutive tiles of a workgroup are
-// separated by one more barrier.
+// Persistent pairs of fused steps over the band tiles (BandTiles); the tile
+// body holds a workgroup barrier and reuses the LDS windows, so consecutive
+// tiles of a workgroup are separated by one more barrier.
 template <int FORM, int COLL, int VAR, int GM, int TH, bool NT>
 __global__ __launch_bounds__(256) void k_ens2_persist(const EnsEntry* __restrict__ tab,
                                                       const int32_t* __restrict__ tile_member, int ntiles,
@@ -179,20 +214,27 @@ __global__ __launch_bounds__(256) void k_ens2_persist(const EnsEntry* __restrict
     using F = Form<FORM>;
     using S = typename F::S;
     using R = typename F::R;
-    const int xcd = static_cast<int>(blockIdx.x & 7u), j = static_cast<int>(blockIdx.x >> 3);
-    const int m = static_cast<int>(gridDim.x >> 3);
-    const int band = (ntiles + 7) >> 3;
-    const int start = xcd * band;
-    const int end = (start + band < ntiles) ? start + band : ntiles;
+    __shared__ int s_claim[2];
+    const BandTiles bt = band_tiles(sync, ntiles);
+    if (threadIdx.x == 0) s_claim[0] = claim_tile(bt);
+    __syncthreads();
+    int k = s_claim[0], p = 0;
     for (int s = 0; s < npairs; ++s) {
         const int par = (parity + s) & 1;
-        for (int t = start + j; t < end; t += m) {
+        const int base = s * bt.B;
+        while (k < base + bt.B) {
+            p ^= 1;
+            int next = 0;
+            if (threadIdx.x == 0) next = claim_tile(bt);
+            const int t = bt.start + (k - base);
             const EnsEntry& e = tab[tile_member[t]];
             const int lt = t - e.tile_start;
             step2_tile<FORM, COLL, VAR, GM, TH, NT>(static_cast<const S*>(e.buf[par]),
                                                     static_cast<S*>(e.buf[par ^ 1]), e.nx, e.ny, e.pitch,
                                                     (lt % e.ntx) * 64, (lt / e.ntx) * TH, coef_of<R>(e));
+            if (threadIdx.x == 0) s_claim[p] = next;
             __syncthreads();
+            k = s_claim[p];
         }
         if (s + 1 < npairs) grid_barrier(sync, static_cast<uint32_t>(s + 1), spin_limit);
     }
@@ -230,7 +272,11 @@ int resident_blocks(const void* kern) {
 template <typename Kern>
 int launch_persistent(Kern kern, const EnsLaunch& a, int blocks) {
     if (!a.sync || blocks < 8 || blocks % 8) return -1;
-    const int64_t max_chunk = static_cast<int64_t>(0xffffffffu) / blocks;
+    // the arrival counters are 32-bit, and a band's tile counter must stay
+    // below 2^31 (steps x band tiles plus one claim per workgroup)
+    const int64_t band = (a.ntiles + 7) / 8;
+    const int64_t max_chunk = std::min<int64_t>(static_cast<int64_t>(0xffffffffu) / blocks,
+                                                ((int64_t{1} << 31) - 1 - blocks) / (band + 1));
     const EnsEntry* tab = a.table;
     const int32_t* map = a.tile_member;
     int done = 0;

@@ -58,8 +58,9 @@ struct EnsEntry {
 };
 // Grid-barrier state of a persistent ensemble launch (device memory owned by
 // the ensemble): eight group arrival counters (one per XCD band of
-// workgroups), the count of groups that have arrived, and this launch's
-// give-up flag are reset by a small kernel before every persistent launch;
+// workgroups), the count of groups that have arrived, this launch's give-up
+// flag and the bands' tile counters are reset by a small kernel before every
+// persistent launch;
 // `failed` is sticky until the host reads it (lbm_ensemble_check).  Each word
 // has a 128-byte line of its own.
 struct EnsSync {
@@ -71,6 +72,7 @@ struct EnsSync {
     Line count;
     Line abort;
     Line failed;
+    Line claim[8];          // tile counters of the eight bands, through all steps of a launch
 };
 struct EnsLaunch {
     const EnsEntry* table;  // device copy of the member table
