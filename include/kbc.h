@@ -367,8 +367,9 @@ int lbm_ensemble_get_fusion(const lbm_ens* e, int32_t* rows);
  *   persistent = 1: ONE launch for all the steps (pairs of fused steps, or
  *     single steps with fusion 1; an odd step left over by the pairs runs as
  *     one more single-step launch): lbm_ensemble_blocks() workgroups, all
- *     resident at once, each looping over its share of the tiles every step,
- *     with a grid barrier (a device-memory arrival counter) between steps.
+ *     resident at once, each taking tiles of its band of the tile range as it
+ *     asks for them (a device-memory counter per band), with a grid barrier
+ *     (device-memory arrival counters) between steps.
  *     Every barrier wait is bounded by the spin limit
  *     (lbm_ensemble_set_spin_limit): a workgroup that polls the counter that
  *     many times marks the launch as failed and every wait of the launch then
