@@ -445,7 +445,18 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         extras["torch_copy_GBs"] = round(2 * a.numel() * 4 / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9, 1)
-        del a, b
+        # two streams read, one written (the adjoint step's pattern: state and
+        # incoming adjoint in, outgoing adjoint out)
+        c = torch.empty_like(a)
+        torch.add(a, b, out=c)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            torch.add(a, b, out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        extras["torch_add_GBs"] = round(3 * a.numel() * 4 / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9, 1)
+        del a, b, c
         torch.cuda.empty_cache()
     if "adjoint" in want:
         progress("adjoint kernel")

@@ -1,10 +1,16 @@
 // kbc_step2.hip -- two fused time steps per launch (temporal blocking) on a
 // single lattice; the tile body is step2_tile (kbc_tile2.hpp).
 //
-// Grid: 1-D, one workgroup per 64 x TH output tile, renumbered so that each
-// XCD sweeps one contiguous band of tiles in row-major order (workgroup b runs
-// on XCD b % 8): tiles whose extended regions overlap in x run close together
-// and their shared loads hit in L2.
+// Grid: 1-D, one workgroup per 64 x TH output tile.  Tiles are numbered in
+// panels of kPanel tile columns (left to right; within a panel row by row,
+// top to bottom) and each XCD sweeps one contiguous band of that numbering
+// (workgroup b runs on XCD b % 8).  Tiles whose extended regions overlap run
+// close together on one XCD, so their shared loads hit in its L2: the
+// x-neighbours are consecutive and the tile below, which re-reads the two
+// ring rows at the tile's bottom edge, is kPanel tiles later (row-major over
+// a 16384-wide lattice it would be 256 tiles later, by which time those rows
+// have left the 4 MB L2).  Only the lines at a panel's side edges are
+// fetched twice.
 #include "kbc_launch.hpp"
 #include "kbc_tile2.hpp"
 
@@ -12,15 +18,48 @@ namespace kbc {
 
 namespace {
 
+#ifndef KBC_PANEL
+#define KBC_PANEL 32
+#endif
+constexpr int kPanel = KBC_PANEL;   // tile columns per panel (a power of two)
+static_assert(kPanel > 0 && (kPanel & (kPanel - 1)) == 0, "panel width must be a power of two");
+
+// Tile (tx, ty) of panel-order index u: full panels of kPanel columns, then
+// one panel of the remaining `last` columns (0 if ntx is a multiple).
+// (With no full panel the order is row-major; otherwise kPanel * nty is at
+// most the tile count, which the host keeps below 2^30.)
+__device__ __forceinline__ void panel_tile(int u, int ntx, int nty, int& tx, int& ty) {
+    const int full = ntx / kPanel;
+    if (full == 0) {
+        ty = u / ntx;
+        tx = u - ty * ntx;
+        return;
+    }
+    const int per_panel = kPanel * nty;
+    const int p = u / per_panel;
+    if (p < full) {
+        const int r = u - p * per_panel;
+        ty = r / kPanel;
+        tx = p * kPanel + (r & (kPanel - 1));
+    } else {
+        const int last = ntx - full * kPanel;
+        const int r = u - full * per_panel;
+        ty = r / last;
+        tx = full * kPanel + (r - ty * last);
+    }
+}
+
 template <int FORM, int COLL, int VAR, int GM, int TH, bool NT>
 __global__ __launch_bounds__(256) void k_step2(const typename Form<FORM>::S* __restrict__ src,
                                                typename Form<FORM>::S* __restrict__ dst, int nx, int ny,
-                                               int64_t pitch, int ntx, int ntiles, int per_xcd,
+                                               int64_t pitch, int ntx, int nty, int per_xcd,
                                                Coef<typename Form<FORM>::R> K) {
     const int b = blockIdx.x;
-    const int t = (b & 7) * per_xcd + (b >> 3);
-    if (t >= ntiles) return;   // the whole workgroup leaves together
-    step2_tile<FORM, COLL, VAR, GM, TH, NT>(src, dst, nx, ny, pitch, (t % ntx) * 64, (t / ntx) * TH, K);
+    const int u = (b & 7) * per_xcd + (b >> 3);
+    if (u >= ntx * nty) return;   // the whole workgroup leaves together
+    int tx, ty;
+    panel_tile(u, ntx, nty, tx, ty);
+    step2_tile<FORM, COLL, VAR, GM, TH, NT>(src, dst, nx, ny, pitch, tx * 64, ty * TH, K);
 }
 
 template <int FORM, int COLL, int VAR, int GM>
@@ -36,7 +75,7 @@ struct Step2Op {
         const int ntiles = static_cast<int>(ntiles64);
         const int per_xcd = (ntiles + 7) / 8;
         k_step2<FORM, COLL, VAR, GM, TH, NT><<<dim3(8u * per_xcd), dim3(256), 0, L.stream>>>(
-            static_cast<const S*>(src), static_cast<S*>(dst), L.nx, L.ny, L.pitch, ntx, ntiles, per_xcd,
+            static_cast<const S*>(src), static_cast<S*>(dst), L.nx, L.ny, L.pitch, ntx, nty, per_xcd,
             make_coef<typename F::R>(L));
         return hipGetLastError() == hipSuccess ? 0 : -2;
     }
