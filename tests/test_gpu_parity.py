@@ -289,6 +289,25 @@ def test_two_fused_steps_are_bitwise_identical(form, coll, var, nx, ny):
 
 
 @pytest.mark.parametrize("form", FORMS)
+def test_fused_panel_order_bitwise(form):
+    """Lattices more than 32 tiles wide number their fused tiles in panels of
+    32 tile columns; a width of 37 tiles plus a ragged column leaves a last
+    panel six tiles wide.  Every tile is still visited exactly once: the
+    fused result equals single steps bit for bit."""
+    nx, ny = 64 * 37 + 5, 40
+    say("panel order", form, nx, ny)
+    ux, uy = inputs.spectral(nx, 8, 0.05, seed=23, ny=ny)
+    outs = []
+    for fusion in ((1, 0), (2, 8), (2, 16), (2, 24)) + (((2, 32),) if form != "f64" else ()):
+        s = Sim(nx, ny, beta_from_nu(1e-4), collision="kbc", variant="B", form=form, fusion=fusion)
+        s.init(ux, uy)
+        s.step(4)
+        outs.append(s.planes(s.state_buffer()).clone())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+@pytest.mark.parametrize("form", FORMS)
 def test_diagnostics_parity(orc, form):
     nx, ny = 67, 45
     say("diagnostics", form)
