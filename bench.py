@@ -182,6 +182,57 @@ def time_c5(dev):
     return out
 
 
+def time_slab(dev, steps=50, slabs=8):
+    """One GPU's share of the 16384^2 workload split in y over `slabs` GPUs:
+    a 16384 x (16384 / slabs) slab whose rows -2, -1 and ny, ny + 1 come
+    from halo buffers (lbm_set_halo).  Before every launch of two fused steps
+    the halo is refreshed the way a multi-GPU run would do it, here from the
+    slab's own edge rows (lbm_get_edge_rows, then two device copies standing
+    in for the sends), all inside the timed region; against the same slab as
+    a periodic lattice with no exchange."""
+    import torch
+    n = 16384
+    h = n // slabs
+    sim = make_sim(n, "f32", "kbc", "B", 1e-4, 3, 32, dev)
+    state = sim.state_buffer()[:h].clone()
+    del sim
+    torch.cuda.empty_cache()
+    from paper_1507_02509_amd.sim import Sim, beta_from_nu
+    res = {"slab": f"{n} x {h}", "slabs": slabs}
+    for mode in ("periodic", "halo"):
+        s = Sim(n, h, beta_from_nu(1e-4), collision="kbc", variant="B", form="f32", device=dev)
+        s.init(np.zeros((h, n)), np.zeros((h, n)), mode="eq")
+        s.state_buffer().copy_(state)
+        lo, hi = s.halo_buffers()
+        send_lo, send_hi = s.halo_buffers()
+
+        def launch():
+            if mode == "halo":
+                s.edge_rows(send_lo, send_hi)
+                lo.copy_(send_hi)
+                hi.copy_(send_lo)
+            s.step(2)
+        if mode == "halo":
+            s.set_halo(lo, hi)
+        for _ in range(5):
+            launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps // 2):
+            launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (2 * (steps // 2))
+        res[mode] = {"ms_per_step": round(ms, 4), "mlups": round(n * h / (ms * 1e-3) / 1e6, 1)}
+        del s
+        torch.cuda.empty_cache()
+    # bytes that would cross to the two neighbours per launch of two steps
+    res["exchange_bytes_per_launch"] = 2 * 2 * 9 * n * 4
+    res["halo_over_periodic_time"] = round(res["halo"]["ms_per_step"] / res["periodic"]["ms_per_step"], 3)
+    return res
+
+
 def time_ensemble(dev, steps=60, persistent_steps=2000):
     """The uneven ensemble: 256 members, N in {128, 256, 512, 1024}, KBC-B FP32.
     (a) the library's default launch (one batched launch over all members'
@@ -312,7 +363,7 @@ def main():
                     help="steps per launch [,fused tile rows], e.g. 1 or 2,16 (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="forms,lbgk,exact,copy,adjoint,rollout,ensemble,accuracy",
+    ap.add_argument("--extras", default="forms,lbgk,exact,copy,adjoint,rollout,ensemble,slab,accuracy",
                     help="comma-separated extra measurements")
     ap.add_argument("--extra-steps", type=int, default=50,
                     help="timed steps for the other forms and the LBGK baseline")
@@ -472,6 +523,9 @@ def main():
     if "ensemble" in want:
         progress("ensemble 256")
         extras["ensemble_256_f32"] = time_ensemble(dev, steps=args.extra_steps)
+    if "slab" in want:
+        progress("slab of an 8-way split")
+        extras["slab_8way_f32"] = time_slab(dev, steps=args.extra_steps)
     if "accuracy" in want:
         progress("form errors")
         extras["accuracy"] = form_errors(n, nu, seed, k0, dev)

@@ -204,6 +204,37 @@ int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t fla
 int lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows);
 int lbm_get_fusion(const lbm_ctx* c, int32_t* rows);
 
+/* Slab mode: the context's lattice is one slab of a larger domain split in y
+ * (one slab per GPU), periodic in x only.  The step's pull (eq. Egeneral:
+ * population i arrives from x - v_i) then reads the two rows on each side of
+ * the slab from the neighbouring slabs instead of wrapping onto itself.
+ * `lo` holds rows -2 and -1, `hi` rows ny and ny + 1, of the state at the
+ * current time, each laid out [2][9][pitch] exactly like the state ([row][population]
+ * [x], storage form, the context's pitch): device memory owned by the caller,
+ * read by every following lbm_step until the next lbm_set_halo.  Both NULL
+ * returns the context to periodic rows (the default); one NULL is
+ * LBM_EINVAL.  While a halo is set:
+ *   - lbm_step(c, n) takes n <= steps per launch (lbm_set_fusion): one
+ *     launch, since the halo holds the neighbours' rows at one time only
+ *     (two rows: enough for two fused steps); the caller refreshes the halo
+ *     between calls.  Larger n is LBM_EINVAL.
+ *   - fused tiles are 8 or 16 rows (LBM_EUNSUPPORTED otherwise) and graph
+ *     replay is off (lbm_set_graph with chunk > 0 is LBM_EINVAL);
+ *   - the context cannot join an ensemble (and lbm_set_halo is LBM_EINVAL
+ *     while it is in one).
+ * Only lbm_step reads the halo: moments, diagnostics, spectra and the
+ * adjoint still treat the slab as periodic in y.  Results equal, bit for bit,
+ * the rows of the whole domain stepped as one periodic lattice. */
+int lbm_set_halo(lbm_ctx* c, const void* lo, const void* hi);
+
+/* The rows a neighbouring slab needs as its halo, from the current state:
+ * rows 0 and 1 into lo_rows (the halo `hi` of the slab below, in -y) and rows
+ * ny - 2 and ny - 1 into hi_rows (the halo `lo` of the slab above), each
+ * [2][9][pitch] in the storage form.  Two device-to-device copies enqueued on
+ * params.stream; both pointers are device memory the caller owns (in a
+ * multi-GPU run, the send buffers of the halo exchange). */
+int lbm_get_edge_rows(lbm_ctx* c, void* lo_rows, void* hi_rows);
+
 /* HIP graph replay for launch-bound (small) lattices.  With chunk >= 2,
  * lbm_step runs every whole chunk of `chunk` steps as one hipGraphLaunch on
  * params.stream and the remainder as direct launches.  The graph of a chunk

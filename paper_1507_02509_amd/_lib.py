@@ -69,6 +69,8 @@ _SIGS = {
     "lbm_spectra": (_c.c_int, [_vp, _c.c_int32, _vp, _vp]),
     "lbm_get_fusion": (_c.c_int, [_vp, _c.POINTER(_c.c_int32)]),
     "lbm_set_graph": (_c.c_int, [_vp, _c.c_int32]),
+    "lbm_set_halo": (_c.c_int, [_vp, _vp, _vp]),
+    "lbm_get_edge_rows": (_c.c_int, [_vp, _vp, _vp]),
     "lbm_get_graph": (_c.c_int, [_vp]),
     "lbm_free": (_c.c_int, [_vp]),
     "lbm_last_error": (_c.c_char_p, []),

@@ -287,6 +287,14 @@ extern "C" {
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (c->L.halo_lo) {
+        // a slab: the halo buffers hold the neighbours' rows at the current
+        // time, enough for one launch
+        if (nsteps > c->fuse)
+            return fail(LBM_EINVAL, "a slab steps at most %d step(s) per call (its halo holds the rows for one launch)",
+                        c->fuse);
+        return step_eager(c, nsteps);
+    }
     if (c->graph_chunk >= 2) {
         for (; nsteps >= c->graph_chunk; nsteps -= c->graph_chunk) {
             const int rc = step_graph(c);
@@ -298,6 +306,7 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
 
 int lbm_set_graph(lbm_ctx* c, int32_t chunk) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (chunk != 0 && c->L.halo_lo) return fail(LBM_EINVAL, "a slab (halo buffers set) does not replay graphs");
     if (chunk != 0 && (chunk < 2 || chunk > (1 << 20)))
         return fail(LBM_EINVAL, "graph chunk must be 0 or in [2, 2^20] (got %d)", chunk);
     if (chunk == c->graph_chunk) return LBM_OK;
@@ -316,6 +325,8 @@ int lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows) {
         return fail(LBM_EINVAL, "rows must be 0 (keep), 8, 16, 24 or 32 (got %d)", rows);
     if (rows == 32 && c->p.form == LBM_F64)
         return fail(LBM_EUNSUPPORTED, "a 32-row fused FP64 tile does not fit the LDS of a CU");
+    if (c->L.halo_lo && (rows == 24 || rows == 32))
+        return fail(LBM_EUNSUPPORTED, "a slab (halo buffers set) runs fused tiles of 8 or 16 rows");
     const int rc = graph_reset(c);
     if (rc) return rc;
     c->fuse = steps_per_launch;
@@ -832,6 +843,33 @@ int ens_build(lbm_ens* e) {
 
 }  // namespace
 
+int lbm_set_halo(lbm_ctx* c, const void* lo, const void* hi) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if ((lo == nullptr) != (hi == nullptr)) return fail(LBM_EINVAL, "set both halo buffers or neither");
+    if (lo && c->ens_refs > 0) return fail(LBM_EINVAL, "the context belongs to a live ensemble");
+    if (lo && c->fuse == 2 && c->fuse_rows != 8 && c->fuse_rows != 16)
+        return fail(LBM_EUNSUPPORTED, "a slab runs fused tiles of 8 or 16 rows (set with lbm_set_fusion)");
+    int rc = graph_reset(c);
+    if (rc) return rc;
+    if (lo) c->graph_chunk = 0;
+    c->L.halo_lo = lo;
+    c->L.halo_hi = hi;
+    return LBM_OK;
+}
+
+int lbm_get_edge_rows(lbm_ctx* c, void* lo_rows, void* hi_rows) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!lo_rows || !hi_rows) return fail(LBM_EINVAL, "lo_rows and hi_rows must not be NULL");
+    const size_t es = c->p.form == LBM_F16DEV_F32 ? 2 : (c->p.form == LBM_F32DEV_F32 ? 4 : 8);
+    const size_t row = 9 * static_cast<size_t>(c->L.pitch) * es;   // one lattice row: nine population rows
+    const char* cur = static_cast<const char*>(c->buf[c->cur]);
+    hipError_t e = hipMemcpyAsync(lo_rows, cur, 2 * row, hipMemcpyDeviceToDevice, c->L.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hi_rows, cur + static_cast<size_t>(c->p.ny - 2) * row, 2 * row, hipMemcpyDeviceToDevice,
+                           c->L.stream);
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "lbm_get_edge_rows");
+}
+
 int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -840,6 +878,7 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
     for (int32_t r = 0; r < count; ++r) {
         const lbm_ctx* c = members[r];
         if (!c) return fail(LBM_EINVAL, "member %d is NULL", r);
+        if (c->L.halo_lo) return fail(LBM_EINVAL, "member %d is a slab (halo buffers set); members are periodic", r);
         if (c->p.form != m0->p.form || c->p.collision != m0->p.collision ||
             (c->p.collision == LBM_KBC && c->p.variant != m0->p.variant) || c->p.gamma_mode != m0->p.gamma_mode ||
             c->p.stream != m0->p.stream)

@@ -16,6 +16,11 @@ struct Lattice {
     double beta, rho0, guard, gamma_fixed;
     hipStream_t stream;
     int adj_frozen;         // adjoint holds gamma at its forward value
+    // slab of a domain split in y: rows -2, -1 (lo) and ny, ny + 1 (hi) of
+    // the current state, [2][9][pitch] each in the storage form; null for a
+    // periodic lattice.  Only the step launches read them.
+    const void* halo_lo = nullptr;
+    const void* halo_hi = nullptr;
 };
 
 // step kernel tile: `width` in {64, 128, 256} nodes, each thread walks `rpt`

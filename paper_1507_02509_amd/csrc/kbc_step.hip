@@ -30,20 +30,21 @@
 
 namespace kbc {
 
-template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
+template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT, bool SLAB>
 __global__ __launch_bounds__(256) void k_step(const typename Form<FORM>::S* __restrict__ src,
                                               typename Form<FORM>::S* __restrict__ dst, int nx,
                                               int ny, int64_t pitch, int ntx, int ntiles,
-                                              int per_xcd, Coef<typename Form<FORM>::R> K) {
+                                              int per_xcd, Coef<typename Form<FORM>::R> K,
+                                              SlabHalo<typename Form<FORM>::S> halo) {
     const int b = blockIdx.x;
     const int t = (b & 7) * per_xcd + (b >> 3);
     if (t >= ntiles) return;
-    step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT>(src, dst, nx, ny, pitch, t % ntx, t / ntx, K);
+    step_tile<FORM, COLL, VAR, GM, TXW, RPT, NT, SLAB>(src, dst, nx, ny, pitch, t % ntx, t / ntx, K, halo);
 }
 
 template <int FORM, int COLL, int VAR, int GM>
 struct StepOp {
-    template <int TXW, int RPT, bool NT>
+    template <int TXW, int RPT, bool NT, bool SLAB = false>
     static int go(const Lattice& L, const void* src, void* dst) {
         using F = Form<FORM>;
         using S = typename F::S;
@@ -54,9 +55,12 @@ struct StepOp {
         if (ntiles64 > (int64_t{1} << 30)) return -1;
         const int ntiles = static_cast<int>(ntiles64);
         const int per_xcd = (ntiles + 7) / 8;
-        k_step<FORM, COLL, VAR, GM, TXW, RPT, NT><<<dim3(8u * per_xcd), dim3(256), 0, L.stream>>>(
+        SlabHalo<S> halo;
+        halo.lo = static_cast<const S*>(L.halo_lo);
+        halo.hi = static_cast<const S*>(L.halo_hi);
+        k_step<FORM, COLL, VAR, GM, TXW, RPT, NT, SLAB><<<dim3(8u * per_xcd), dim3(256), 0, L.stream>>>(
             static_cast<const S*>(src), static_cast<S*>(dst), L.nx, L.ny, L.pitch, ntx, ntiles, per_xcd,
-            make_coef<typename F::R>(L));
+            make_coef<typename F::R>(L), halo);
         return hipGetLastError() == hipSuccess ? 0 : -2;
     }
     template <bool NT>
@@ -74,7 +78,22 @@ struct StepOp {
             default: return -1;
         }
     }
+    // a slab (halo rows from buffers) runs one of the three default tile
+    // shapes: 256 x 4 (FP16), 256 x 1 (FP32) or 128 x 2 (FP64), the
+    // requested one if it is among them
+    template <bool NT>
+    static int slab_shape(const Lattice& L, const void* src, void* dst, const StepShape& sh) {
+        switch (sh.width * 16 + sh.rpt) {
+            case 256 * 16 + 4: return go<4, 4, NT, true>(L, src, dst);
+            case 128 * 16 + 2: return go<2, 2, NT, true>(L, src, dst);
+            case 256 * 16 + 1: return go<4, 1, NT, true>(L, src, dst);
+            default:
+                return FORM == F16 ? go<4, 4, NT, true>(L, src, dst)
+                                   : (FORM == F64 ? go<2, 2, NT, true>(L, src, dst) : go<4, 1, NT, true>(L, src, dst));
+        }
+    }
     static int run(const Lattice& L, const void* src, void* dst, const StepShape& sh) {
+        if (L.halo_lo) return sh.nt ? slab_shape<true>(L, src, dst, sh) : slab_shape<false>(L, src, dst, sh);
         return sh.nt ? shape<true>(L, src, dst, sh) : shape<false>(L, src, dst, sh);
     }
 };

@@ -49,22 +49,23 @@ __device__ __forceinline__ void panel_tile(int u, int ntx, int nty, int& tx, int
     }
 }
 
-template <int FORM, int COLL, int VAR, int GM, int TH, bool NT>
+template <int FORM, int COLL, int VAR, int GM, int TH, bool NT, bool SLAB>
 __global__ __launch_bounds__(256) void k_step2(const typename Form<FORM>::S* __restrict__ src,
                                                typename Form<FORM>::S* __restrict__ dst, int nx, int ny,
                                                int64_t pitch, int ntx, int nty, int per_xcd,
-                                               Coef<typename Form<FORM>::R> K) {
+                                               Coef<typename Form<FORM>::R> K,
+                                               SlabHalo<typename Form<FORM>::S> halo) {
     const int b = blockIdx.x;
     const int u = (b & 7) * per_xcd + (b >> 3);
     if (u >= ntx * nty) return;   // the whole workgroup leaves together
     int tx, ty;
     panel_tile(u, ntx, nty, tx, ty);
-    step2_tile<FORM, COLL, VAR, GM, TH, NT>(src, dst, nx, ny, pitch, tx * 64, ty * TH, K);
+    step2_tile<FORM, COLL, VAR, GM, TH, NT, SLAB>(src, dst, nx, ny, pitch, tx * 64, ty * TH, K, halo);
 }
 
 template <int FORM, int COLL, int VAR, int GM>
 struct Step2Op {
-    template <int TH, bool NT>
+    template <int TH, bool NT, bool SLAB = false>
     static int go(const Lattice& L, const void* src, void* dst) {
         using F = Form<FORM>;
         using S = typename F::S;
@@ -74,9 +75,12 @@ struct Step2Op {
         if (ntiles64 > (int64_t{1} << 30)) return -1;
         const int ntiles = static_cast<int>(ntiles64);
         const int per_xcd = (ntiles + 7) / 8;
-        k_step2<FORM, COLL, VAR, GM, TH, NT><<<dim3(8u * per_xcd), dim3(256), 0, L.stream>>>(
+        SlabHalo<S> halo;
+        halo.lo = static_cast<const S*>(L.halo_lo);
+        halo.hi = static_cast<const S*>(L.halo_hi);
+        k_step2<FORM, COLL, VAR, GM, TH, NT, SLAB><<<dim3(8u * per_xcd), dim3(256), 0, L.stream>>>(
             static_cast<const S*>(src), static_cast<S*>(dst), L.nx, L.ny, L.pitch, ntx, nty, per_xcd,
-            make_coef<typename F::R>(L));
+            make_coef<typename F::R>(L), halo);
         return hipGetLastError() == hipSuccess ? 0 : -2;
     }
     template <int TH>
@@ -90,6 +94,16 @@ struct Step2Op {
         }
     }
     static int run(const Lattice& L, const void* src, void* dst, int rows, int nt_flag) {
+        // a slab (halo rows from buffers): 8- and 16-row tiles
+        if (L.halo_lo) {
+            switch (rows * 2 + (nt_flag ? 1 : 0)) {
+                case 8 * 2: return go<8, false, true>(L, src, dst);
+                case 8 * 2 + 1: return go<8, true, true>(L, src, dst);
+                case 16 * 2: return go<16, false, true>(L, src, dst);
+                case 16 * 2 + 1: return go<16, true, true>(L, src, dst);
+                default: return -1;
+            }
+        }
         switch (rows) {
             case 8: return nt<8>(L, src, dst, nt_flag);
             case 16: return nt<16>(L, src, dst, nt_flag);

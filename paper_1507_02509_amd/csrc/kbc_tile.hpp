@@ -70,17 +70,46 @@ __device__ __forceinline__ S ld_at(gptr<const S> base, uint32_t off) {
                                             lane_off(off));
 }
 
+// A slab is a lattice that is one piece of a domain split in y (one piece
+// per GPU): it is periodic in x, and its rows -2, -1 and ny, ny + 1 are not
+// its own rows wrapped but the neighbouring pieces' edge rows, kept in two
+// caller-owned halo buffers laid out [2][9][pitch] like the state (`lo`: rows
+// -2, -1; `hi`: rows ny, ny + 1).  Null pointers for a periodic lattice.
+template <typename S>
+struct SlabHalo {
+    const S* lo = nullptr;
+    const S* hi = nullptr;
+};
+
+// Population-i row y (uniform, -2 <= y <= ny + 1) of a slab's state.
+template <typename S>
+__device__ __forceinline__ gptr<const S> slab_row(const S* base, const SlabHalo<S>& h, int y, int i, int ny,
+                                                  int64_t pitch) {
+    const S* b = base;
+    int r = y;
+    if (y < 0) {
+        b = h.lo;
+        r = y + 2;
+    } else if (y >= ny) {
+        b = h.hi;
+        r = y - ny;
+    }
+    return row_ptr(b, r, i, pitch);
+}
+
 // Tile (tx, ty) of a lattice: 64 * TXW nodes wide, (4 / TXW) * RPT rows tall,
 // for the 256 threads of the calling workgroup.  Every wave covers 64
 // consecutive nodes of one row, so the row index is uniform across the wave:
 // the nine source rows (three y values, nine populations) and nine destination
 // rows are scalar bases, and a lane's loads and stores differ from them only
-// by the 32-bit byte offsets of x - 1, x and x + 1.
-template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT>
+// by the 32-bit byte offsets of x - 1, x and x + 1.  SLAB: rows -1 and ny
+// come from the halo buffers instead of wrapping.
+template <int FORM, int COLL, int VAR, int GM, int TXW, int RPT, bool NT, bool SLAB = false>
 __device__ __forceinline__ void step_tile(const typename Form<FORM>::S* __restrict__ src,
                                           typename Form<FORM>::S* __restrict__ dst, int nx, int ny,
                                           int64_t pitch, int tx, int ty,
-                                          const Coef<typename Form<FORM>::R>& K) {
+                                          const Coef<typename Form<FORM>::R>& K,
+                                          const SlabHalo<typename Form<FORM>::S>& halo = {}) {
     using F = Form<FORM>;
     using R = typename F::R;
     using S = typename F::S;
@@ -97,18 +126,24 @@ __device__ __forceinline__ void step_tile(const typename Form<FORM>::S* __restri
     for (int r = 0; r < RPT; ++r) {
         const int y = y0 + r;
         if (y >= ny) return;
-        const int ym = (y == 0) ? ny - 1 : y - 1;
-        const int yp = (y == ny - 1) ? 0 : y + 1;
+        const int ym = SLAB ? y - 1 : ((y == 0) ? ny - 1 : y - 1);
+        const int yp = SLAB ? y + 1 : ((y == ny - 1) ? 0 : y + 1);
+        auto in = [&](int yy, int i) {
+            if constexpr (SLAB)
+                return slab_row(src, halo, yy, i, ny, pitch);
+            else
+                return row_ptr(src, yy, i, pitch);
+        };
         R g[9];
-        g[0] = F::dec(ld_at(row_ptr(src, y, 0, pitch), c0), 0);
-        g[1] = F::dec(ld_at(row_ptr(src, y, 1, pitch), cm), 1);
-        g[2] = F::dec(ld_at(row_ptr(src, ym, 2, pitch), c0), 2);
-        g[3] = F::dec(ld_at(row_ptr(src, y, 3, pitch), cp), 3);
-        g[4] = F::dec(ld_at(row_ptr(src, yp, 4, pitch), c0), 4);
-        g[5] = F::dec(ld_at(row_ptr(src, ym, 5, pitch), cm), 5);
-        g[6] = F::dec(ld_at(row_ptr(src, ym, 6, pitch), cp), 6);
-        g[7] = F::dec(ld_at(row_ptr(src, yp, 7, pitch), cp), 7);
-        g[8] = F::dec(ld_at(row_ptr(src, yp, 8, pitch), cm), 8);
+        g[0] = F::dec(ld_at(in(y, 0), c0), 0);
+        g[1] = F::dec(ld_at(in(y, 1), cm), 1);
+        g[2] = F::dec(ld_at(in(ym, 2), c0), 2);
+        g[3] = F::dec(ld_at(in(y, 3), cp), 3);
+        g[4] = F::dec(ld_at(in(yp, 4), c0), 4);
+        g[5] = F::dec(ld_at(in(ym, 5), cm), 5);
+        g[6] = F::dec(ld_at(in(ym, 6), cp), 6);
+        g[7] = F::dec(ld_at(in(yp, 7), cp), 7);
+        g[8] = F::dec(ld_at(in(yp, 8), cm), 8);
         collide<R, COLL, VAR, GM>(g, K);
 #pragma unroll
         for (int i = 0; i < 9; ++i) st_at<NT>(row_ptr(dst, y, i, pitch), c0, F::enc(g[i], i));

@@ -55,11 +55,15 @@ __device__ __forceinline__ int wrap1(int v, int n) {
 
 // Two fused steps on the output tile with corner (x0, y0), for the 256
 // threads of the calling workgroup (all of which must call it: it holds a
-// workgroup barrier).
-template <int FORM, int COLL, int VAR, int GM, int TH, bool NT>
+// workgroup barrier).  SLAB: the rows beyond the slab's edges, -2, -1 and
+// ny, ny + 1, come from the halo buffers (SlabHalo) instead of wrapping;
+// extended rows past row ny (a ragged last tile) only feed output rows the
+// tile does not store, and load row ny instead.
+template <int FORM, int COLL, int VAR, int GM, int TH, bool NT, bool SLAB = false>
 __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restrict__ src,
                                            typename Form<FORM>::S* __restrict__ dst, int nx, int ny,
-                                           int64_t pitch, int x0, int y0, const Coef<typename Form<FORM>::R>& K) {
+                                           int64_t pitch, int x0, int y0, const Coef<typename Form<FORM>::R>& K,
+                                           const SlabHalo<typename Form<FORM>::S>& halo = {}) {
     using F = Form<FORM>;
     using R = typename F::R;
     using S = typename F::S;
@@ -79,18 +83,31 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
         const uint32_t cm = static_cast<uint32_t>(gx == 0 ? nx - 1 : gx - 1) * sizeof(S);
         const uint32_t cp = static_cast<uint32_t>(gx == nx - 1 ? 0 : gx + 1) * sizeof(S);
         auto load_row = [&](int ey, S (&v)[9]) {
-            const int y = wrap_uniform(y0 - 1 + ey, ny);
-            const int ym = (y == 0) ? ny - 1 : y - 1;
-            const int yp = (y == ny - 1) ? 0 : y + 1;
-            v[0] = ld_at(row_ptr(src, y, 0, pitch), c0);
-            v[1] = ld_at(row_ptr(src, y, 1, pitch), cm);
-            v[2] = ld_at(row_ptr(src, ym, 2, pitch), c0);
-            v[3] = ld_at(row_ptr(src, y, 3, pitch), cp);
-            v[4] = ld_at(row_ptr(src, yp, 4, pitch), c0);
-            v[5] = ld_at(row_ptr(src, ym, 5, pitch), cm);
-            v[6] = ld_at(row_ptr(src, ym, 6, pitch), cp);
-            v[7] = ld_at(row_ptr(src, yp, 7, pitch), cp);
-            v[8] = ld_at(row_ptr(src, yp, 8, pitch), cm);
+            int y, ym, yp;
+            if constexpr (SLAB) {
+                y = y0 - 1 + ey < ny ? y0 - 1 + ey : ny;
+                ym = y - 1;
+                yp = y + 1;
+            } else {
+                y = wrap_uniform(y0 - 1 + ey, ny);
+                ym = (y == 0) ? ny - 1 : y - 1;
+                yp = (y == ny - 1) ? 0 : y + 1;
+            }
+            auto in = [&](int yy, int i) {
+                if constexpr (SLAB)
+                    return slab_row(src, halo, yy, i, ny, pitch);
+                else
+                    return row_ptr(src, yy, i, pitch);
+            };
+            v[0] = ld_at(in(y, 0), c0);
+            v[1] = ld_at(in(y, 1), cm);
+            v[2] = ld_at(in(ym, 2), c0);
+            v[3] = ld_at(in(y, 3), cp);
+            v[4] = ld_at(in(yp, 4), c0);
+            v[5] = ld_at(in(ym, 5), cm);
+            v[6] = ld_at(in(ym, 6), cp);
+            v[7] = ld_at(in(yp, 7), cp);
+            v[8] = ld_at(in(yp, 8), cm);
         };
         auto row = [&](int ey, const S (&v)[9]) {
             R g[9];
@@ -132,12 +149,23 @@ __device__ __forceinline__ void step2_tile(const typename Form<FORM>::S* __restr
             const int side = k / EH;
             const int ey = k - side * EH;
             const int gx = pmod(side ? x0 + TW : x0 - 1, nx);
-            const int y = pmod(y0 - 1 + ey, ny);
             R g[9];
+            if constexpr (SLAB) {
+                const int y = y0 - 1 + ey < ny ? y0 - 1 + ey : ny;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const int xs = wrap1(gx - kCx[i], nx), ys = wrap1(y - kCy[i], ny);
-                g[i] = F::dec(src[(static_cast<int64_t>(ys) * 9 + i) * pitch + xs], i);
+                for (int i = 0; i < 9; ++i) {
+                    const int xs = wrap1(gx - kCx[i], nx), ys = y - kCy[i];
+                    const S* b = ys < 0 ? halo.lo : (ys >= ny ? halo.hi : src);
+                    const int r = ys < 0 ? ys + 2 : (ys >= ny ? ys - ny : ys);
+                    g[i] = F::dec(b[(static_cast<int64_t>(r) * 9 + i) * pitch + xs], i);
+                }
+            } else {
+                const int y = pmod(y0 - 1 + ey, ny);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int xs = wrap1(gx - kCx[i], nx), ys = wrap1(y - kCy[i], ny);
+                    g[i] = F::dec(src[(static_cast<int64_t>(ys) * 9 + i) * pitch + xs], i);
+                }
             }
             collide<R, COLL, VAR, GM>(g, K);
             // node (-1 or 64, ey - 1): only the populations that move into

@@ -126,6 +126,32 @@ class Sim:
         self.lib.lbm_get_fusion(self.ctx, ctypes.byref(r))
         return int(r.value)
 
+    # ------------------------------------------------------- slab of a domain
+    def halo_buffers(self) -> tuple[torch.Tensor, torch.Tensor]:
+        """Two zeroed [2, 9, pitch] buffers of the storage dtype: the shape of
+        a slab's halo (lbm_set_halo) and of its edge rows (lbm_get_edge_rows)."""
+        dt = _TORCH_STORE[self.form]
+        return (torch.zeros((2, 9, self.pitch), dtype=dt, device=self.device),
+                torch.zeros((2, 9, self.pitch), dtype=dt, device=self.device))
+
+    def set_halo(self, lo: torch.Tensor | None, hi: torch.Tensor | None):
+        """Make this lattice one slab of a domain split in y: rows -2, -1
+        come from `lo` and rows ny, ny + 1 from `hi` ([2, 9, pitch] each, kept
+        alive by the caller and refreshed between steps); None, None returns
+        to periodic rows (include/kbc.h, lbm_set_halo)."""
+        for t in (lo, hi):
+            if t is not None:
+                assert t.shape == (2, 9, self.pitch) and t.dtype == _TORCH_STORE[self.form] and t.is_contiguous()
+        self._halo = (lo, hi)
+        L.check(self.lib.lbm_set_halo(self.ctx, L.ptr(lo), L.ptr(hi)), "lbm_set_halo")
+
+    def edge_rows(self, lo_rows: torch.Tensor, hi_rows: torch.Tensor):
+        """Rows 0, 1 into lo_rows and rows ny - 2, ny - 1 into hi_rows (the
+        neighbours' halos), enqueued on the library's stream."""
+        for t in (lo_rows, hi_rows):
+            assert t.shape == (2, 9, self.pitch) and t.dtype == _TORCH_STORE[self.form] and t.is_contiguous()
+        L.check(self.lib.lbm_get_edge_rows(self.ctx, L.ptr(lo_rows), L.ptr(hi_rows)), "lbm_get_edge_rows")
+
     def set_tile(self, width: int, rows_per_thread: int = 1, nontemporal: bool = False):
         L.check(self.lib.lbm_set_tile(self.ctx, int(width), int(rows_per_thread), 1 if nontemporal else 0),
                 "lbm_set_tile")
