@@ -142,7 +142,8 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
  * steps is one launch (two fused pull-stream + collide steps, the first step's
  * result kept in LDS; see lbm_set_fusion) and an odd remainder one single-step
  * launch; each launch reads one buffer and writes the other.  Enqueues only;
- * does no value checks (see lbm_diagnostics). */
+ * does no value checks (see lbm_diagnostics).  A slab (lbm_set_halo) takes
+ * at most one launch's steps per call. */
 int lbm_step(lbm_ctx* c, int32_t nsteps);
 
 /* Density, velocity and (optionally) the stabiliser gamma the next collision
