@@ -18,7 +18,9 @@
  *
  * Lattice conventions:
  *   velocity order i = 0..8: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
- *   (-1,-1) (1,-1); weights W = 4/9, 1/9 (x4), 1/36 (x4); periodic in x and y.
+ *   (-1,-1) (1,-1); weights W = 4/9, 1/9 (x4), 1/36 (x4); periodic in x and y
+ *   (a slab of a domain split in y takes its rows beyond y = 0 .. ny - 1 from
+ *   halo buffers instead: lbm_set_halo).
  *
  * Storage (device memory owned by the caller, e.g. torch tensors):
  *   a population buffer holds, for every lattice row y, the nine population
