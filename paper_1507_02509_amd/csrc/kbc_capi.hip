@@ -325,7 +325,7 @@ int lbm_set_fusion(lbm_ctx* c, int32_t steps_per_launch, int32_t rows) {
         return fail(LBM_EINVAL, "rows must be 0 (keep), 8, 16, 24 or 32 (got %d)", rows);
     if (rows == 32 && c->p.form == LBM_F64)
         return fail(LBM_EUNSUPPORTED, "a 32-row fused FP64 tile does not fit the LDS of a CU");
-    if (c->L.halo_lo && (rows == 24 || rows == 32))
+    if (c->L.halo_lo && (rows ? rows : c->fuse_rows) != 8 && (rows ? rows : c->fuse_rows) != 16)
         return fail(LBM_EUNSUPPORTED, "a slab (halo buffers set) runs fused tiles of 8 or 16 rows");
     const int rc = graph_reset(c);
     if (rc) return rc;
@@ -847,7 +847,7 @@ int lbm_set_halo(lbm_ctx* c, const void* lo, const void* hi) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if ((lo == nullptr) != (hi == nullptr)) return fail(LBM_EINVAL, "set both halo buffers or neither");
     if (lo && c->ens_refs > 0) return fail(LBM_EINVAL, "the context belongs to a live ensemble");
-    if (lo && c->fuse == 2 && c->fuse_rows != 8 && c->fuse_rows != 16)
+    if (lo && c->fuse_rows != 8 && c->fuse_rows != 16)
         return fail(LBM_EUNSUPPORTED, "a slab runs fused tiles of 8 or 16 rows (set with lbm_set_fusion)");
     int rc = graph_reset(c);
     if (rc) return rc;
