@@ -242,6 +242,59 @@ def test_rollout_gradient_matches_finite_differences_f64():
     assert b.grad.item() == pytest.approx(fdb, rel=1e-5)
 
 
+# FP32 bars: measured FP32 vs FP64 gradient differences are 7.0e-7 (B, 300
+# steps) and 1.75e-3 (D, 2000 steps; the guard's branch changes under FP32
+# rounding at a few nodes move the gradient more)
+@pytest.mark.parametrize("variant,guard,nsteps,f32_tol", [("B", 1e-12, 300, 5e-6), ("D", 1e-4, 2000, 1e-2)])
+def test_rollout_gradient_16x16_finite_differences(variant, guard, nsteps, f32_tol):
+    """The adjoint workload's loss and gradient on a 16 x 16 lattice (KBC,
+    seeded turbulence-like start, nu = 1e-3, loss 1/2 |u(T) - u_t|^2): the
+    FP64 rollout gradient against central finite differences of the FP64
+    forward along a seeded direction (and in beta), and the FP32 rollout
+    gradient against the FP64 one.  Variant D with guard 1e-4 is the KBC
+    configuration the 2000-step benchmark rollout uses; model B with the
+    default guard is checked over 300 steps, where its gradient still means
+    something."""
+    n = 16
+    say("16x16 rollout grad vs FD", variant, guard, nsteps)
+    beta = beta_from_nu(1e-3)
+    ux0, uy0 = inputs.spectral(n, 2, 0.05, seed=61)
+    tx, ty = (torch.from_numpy(a).cuda() for a in inputs.spectral(n, 2, 0.03, seed=62))
+    kw = dict(variant=variant, gamma_guard=guard)
+    grads = {}
+    for form in ("f64", "f32"):
+        u0x = torch.from_numpy(ux0).cuda().requires_grad_(True)
+        u0y = torch.from_numpy(uy0).cuda().requires_grad_(True)
+        b = torch.tensor(beta, dtype=torch.float64, device="cuda", requires_grad=True)
+        _, ux, uy = rollout(u0x, u0y, b, nsteps, form=form, **kw)
+        velocity_loss(ux, uy, tx, ty).backward()
+        grads[form] = (torch.cat([u0x.grad.flatten(), u0y.grad.flatten()]), b.grad.item())
+    rng = np.random.default_rng(63)
+    vx = torch.from_numpy(rng.standard_normal((n, n))).cuda()
+    vy = torch.from_numpy(rng.standard_normal((n, n))).cuda()
+
+    def L(ex, ey, bb):
+        with torch.no_grad():
+            _, a, c = rollout(torch.from_numpy(ux0).cuda() + ex, torch.from_numpy(uy0).cuda() + ey, bb, nsteps,
+                              form="f64", **kw)
+            return velocity_loss(a, c, tx, ty).item()
+    # steps small enough that no node's guard decision changes between the
+    # two evaluations (as in the 512^2 test)
+    h = 1e-9
+    fd = (L(h * vx, h * vy, beta) - L(-h * vx, -h * vy, beta)) / (2 * h)
+    g64, b64 = grads["f64"]
+    ad = float((g64 * torch.cat([vx.flatten(), vy.flatten()])).sum())
+    hb = 1e-9
+    fdb = (L(0, 0, beta + hb) - L(0, 0, beta - hb)) / (2 * hb)
+    g32, b32 = grads["f32"]
+    rel32 = float(torch.linalg.norm(g32 - g64) / torch.linalg.norm(g64))
+    say(f"  directional {ad:.6e} FD {fd:.6e}; dL/dbeta {b64:.6e} FD {fdb:.6e}; FP32 vs FP64 {rel32:.2e}")
+    assert ad == pytest.approx(fd, rel=1e-5)
+    assert b64 == pytest.approx(fdb, rel=1e-4)
+    assert rel32 < f32_tol
+    assert b32 == pytest.approx(b64, rel=f32_tol)
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     nx, ny, nsteps = 70, 33, 23
     say("checkpoint invariance")
