@@ -242,9 +242,8 @@ def test_rollout_gradient_matches_finite_differences_f64():
     assert b.grad.item() == pytest.approx(fdb, rel=1e-5)
 
 
-# FP32 bars: measured FP32 vs FP64 gradient differences are 7.0e-7 (B, 300
-# steps) and 1.75e-3 (D, 2000 steps; the guard's branch changes under FP32
-# rounding at a few nodes move the gradient more)
+# FP32 bars: the measured FP32 vs FP64 gradient differences are 7.0e-7 (B,
+# 300 steps) and 1.75e-3 (D, 2000 steps)
 @pytest.mark.parametrize("variant,guard,nsteps,f32_tol", [("B", 1e-12, 300, 5e-6), ("D", 1e-4, 2000, 1e-2)])
 def test_rollout_gradient_16x16_finite_differences(variant, guard, nsteps, f32_tol):
     """The adjoint workload's loss and gradient on a 16 x 16 lattice (KBC,
