@@ -313,6 +313,19 @@ int lbm_adjoint_seed(lbm_ctx* c, const void* state, const double* dL_drho, const
  * lam_out = dL/df^n and adds the step's dL/dbeta to *dbeta. */
 int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta);
 
+/* lbm_adjoint_step of a slab of a domain split in y (see lbm_set_halo): the
+ * adjoint step reads the state f^n at x - v_i and the incoming adjoint at
+ * x + v_i, so rows -1 and ny of both come from the neighbouring slabs.
+ * state_lo / state_hi: rows -2, -1 and ny, ny + 1 of `state`, [2][9][pitch]
+ * in the storage form (the layout of lbm_set_halo; the step reads rows -1
+ * and ny); lam_lo / lam_hi: the same rows of lam_in, [2][9][pitch] of the
+ * adjoint type.  Device memory owned by the caller, read during this call's
+ * work only.  lambda^n equals, bit for bit, the rows of the whole domain's
+ * adjoint step; *dbeta receives this slab's share of dL/dbeta (the whole
+ * domain's is the sum over slabs, equal up to summation order). */
+int lbm_adjoint_step_slab(lbm_ctx* c, const void* state, const void* state_lo, const void* state_hi,
+                          const void* lam_in, const void* lam_lo, const void* lam_hi, void* lam_out, double* dbeta);
+
 /* lbm_adjoint_step for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same arguments, kernels and results, bit for bit, but the step's

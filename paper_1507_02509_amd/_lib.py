@@ -90,6 +90,7 @@ _SIGS = {
     "lbm_step_buffers": (_c.c_int, [_vp, _vp, _vp]),
     "lbm_adjoint_seed": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_step": (_c.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "lbm_adjoint_step_slab": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_segment": (_c.c_int, [_vp, _vp, _c.POINTER(_vp), _c.c_int32, _vp, _vp, _vp,
                                        _c.POINTER(_c.c_int32)]),
     "lbm_adjoint_init": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int32, _vp, _vp, _vp, _vp]),

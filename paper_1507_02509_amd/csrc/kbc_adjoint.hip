@@ -102,13 +102,17 @@ inline int adj_rows_per_thread(const Lattice& L) {
 constexpr int kFold = 2048;   // partials per k_fold workgroup
 
 // The adjoint step of workgroup index bidx (the 256 threads of the calling
-// workgroup must all call it: it holds a workgroup barrier).
-template <int FORM, int COLL, int VAR, int GM, bool FROZEN, int RPT>
+// workgroup must all call it: it holds a workgroup barrier).  SLAB: rows -1
+// and ny of the state and of the incoming adjoint come from halo buffers
+// (SlabHalo, kbc_tile.hpp) instead of wrapping.
+template <int FORM, int COLL, int VAR, int GM, bool FROZEN, int RPT, bool SLAB = false>
 __device__ __forceinline__ void adj_tile(const typename Form<FORM>::S* __restrict__ state,
                                          const typename Form<FORM>::R* __restrict__ lin,
                                          typename Form<FORM>::R* __restrict__ lout, int nx, int ny,
                                          int64_t pitch, int ntx, int nty, const Coef<typename Form<FORM>::R>& K,
-                                         double* __restrict__ partials, unsigned bidx) {
+                                         double* __restrict__ partials, unsigned bidx,
+                                         const SlabHalo<typename Form<FORM>::S>& sh = {},
+                                         const SlabHalo<typename Form<FORM>::R>& lh = {}) {
     using F = Form<FORM>;
     using R = typename F::R;
     using S = typename F::S;
@@ -143,28 +147,40 @@ __device__ __forceinline__ void adj_tile(const typename Form<FORM>::S* __restric
         const uint32_t sS = sizeof(S), sR = sizeof(R);
         const uint32_t x0 = static_cast<uint32_t>(x);
         auto load = [&](int yu, R (&g)[9], R (&mu)[9]) {
-            const int ym = (yu == 0) ? ny - 1 : yu - 1;
-            const int yp = (yu == ny - 1) ? 0 : yu + 1;
+            const int ym = SLAB ? yu - 1 : ((yu == 0) ? ny - 1 : yu - 1);
+            const int yp = SLAB ? yu + 1 : ((yu == ny - 1) ? 0 : yu + 1);
+            auto st = [&](int yy, int i) {
+                if constexpr (SLAB)
+                    return slab_row(state, sh, yy, i, ny, pitch);
+                else
+                    return row_ptr(state, yy, i, pitch);
+            };
+            auto la = [&](int yy, int i) {
+                if constexpr (SLAB)
+                    return slab_row(lin, lh, yy, i, ny, pitch);
+                else
+                    return row_ptr(lin, yy, i, pitch);
+            };
             // f^n_i(x) sits at x - v_i
-            g[0] = F::dec(ld_at(row_ptr(state, yu, 0, pitch), x0 * sS), 0);
-            g[1] = F::dec(ld_at(row_ptr(state, yu, 1, pitch), xm * sS), 1);
-            g[2] = F::dec(ld_at(row_ptr(state, ym, 2, pitch), x0 * sS), 2);
-            g[3] = F::dec(ld_at(row_ptr(state, yu, 3, pitch), xp * sS), 3);
-            g[4] = F::dec(ld_at(row_ptr(state, yp, 4, pitch), x0 * sS), 4);
-            g[5] = F::dec(ld_at(row_ptr(state, ym, 5, pitch), xm * sS), 5);
-            g[6] = F::dec(ld_at(row_ptr(state, ym, 6, pitch), xp * sS), 6);
-            g[7] = F::dec(ld_at(row_ptr(state, yp, 7, pitch), xp * sS), 7);
-            g[8] = F::dec(ld_at(row_ptr(state, yp, 8, pitch), xm * sS), 8);
+            g[0] = F::dec(ld_at(st(yu, 0), x0 * sS), 0);
+            g[1] = F::dec(ld_at(st(yu, 1), xm * sS), 1);
+            g[2] = F::dec(ld_at(st(ym, 2), x0 * sS), 2);
+            g[3] = F::dec(ld_at(st(yu, 3), xp * sS), 3);
+            g[4] = F::dec(ld_at(st(yp, 4), x0 * sS), 4);
+            g[5] = F::dec(ld_at(st(ym, 5), xm * sS), 5);
+            g[6] = F::dec(ld_at(st(ym, 6), xp * sS), 6);
+            g[7] = F::dec(ld_at(st(yp, 7), xp * sS), 7);
+            g[8] = F::dec(ld_at(st(yp, 8), xm * sS), 8);
             // mu_i(x) = lam^{n+1}_i(x + v_i)
-            mu[0] = ld_at(row_ptr(lin, yu, 0, pitch), x0 * sR);
-            mu[1] = ld_at(row_ptr(lin, yu, 1, pitch), xp * sR);
-            mu[2] = ld_at(row_ptr(lin, yp, 2, pitch), x0 * sR);
-            mu[3] = ld_at(row_ptr(lin, yu, 3, pitch), xm * sR);
-            mu[4] = ld_at(row_ptr(lin, ym, 4, pitch), x0 * sR);
-            mu[5] = ld_at(row_ptr(lin, yp, 5, pitch), xp * sR);
-            mu[6] = ld_at(row_ptr(lin, yp, 6, pitch), xm * sR);
-            mu[7] = ld_at(row_ptr(lin, ym, 7, pitch), xm * sR);
-            mu[8] = ld_at(row_ptr(lin, ym, 8, pitch), xp * sR);
+            mu[0] = ld_at(la(yu, 0), x0 * sR);
+            mu[1] = ld_at(la(yu, 1), xp * sR);
+            mu[2] = ld_at(la(yp, 2), x0 * sR);
+            mu[3] = ld_at(la(yu, 3), xm * sR);
+            mu[4] = ld_at(la(ym, 4), x0 * sR);
+            mu[5] = ld_at(la(yp, 5), xp * sR);
+            mu[6] = ld_at(la(yp, 6), xm * sR);
+            mu[7] = ld_at(la(ym, 7), xm * sR);
+            mu[8] = ld_at(la(ym, 8), xp * sR);
         };
         auto finish = [&](int yu, const R (&g)[9], const R (&mu)[9]) {
             R lam[9], dbn;
@@ -190,14 +206,17 @@ __device__ __forceinline__ void adj_tile(const typename Form<FORM>::S* __restric
     if (threadIdx.x == 0) partials[bidx] = s;
 }
 
-template <int FORM, int COLL, int VAR, int GM, bool FROZEN, int RPT>
+template <int FORM, int COLL, int VAR, int GM, bool FROZEN, int RPT, bool SLAB>
 __global__ __launch_bounds__(256) void k_adj_step(const typename Form<FORM>::S* __restrict__ state,
                                                   const typename Form<FORM>::R* __restrict__ lin,
                                                   typename Form<FORM>::R* __restrict__ lout, int nx,
                                                   int ny, int64_t pitch, int ntx, int nty,
                                                   Coef<typename Form<FORM>::R> K,
-                                                  double* __restrict__ partials) {
-    adj_tile<FORM, COLL, VAR, GM, FROZEN, RPT>(state, lin, lout, nx, ny, pitch, ntx, nty, K, partials, blockIdx.x);
+                                                  double* __restrict__ partials,
+                                                  SlabHalo<typename Form<FORM>::S> sh,
+                                                  SlabHalo<typename Form<FORM>::R> lh) {
+    adj_tile<FORM, COLL, VAR, GM, FROZEN, RPT, SLAB>(state, lin, lout, nx, ny, pitch, ntx, nty, K, partials,
+                                                     blockIdx.x, sh, lh);
 }
 
 // An adjoint step and, in the same grid, one forward step between two other
@@ -354,10 +373,24 @@ struct AdjStepOp {
         using F = Form<FORM>;
         using R = typename F::R;
         using S = typename F::S;
+        if (L.adj_halo[0]) {   // a slab (no fused forward part: checked by go)
+            SlabHalo<S> sh;
+            sh.lo = static_cast<const S*>(L.adj_halo[0]);
+            sh.hi = static_cast<const S*>(L.adj_halo[1]);
+            SlabHalo<R> lh;
+            lh.lo = static_cast<const R*>(L.adj_halo[2]);
+            lh.hi = static_cast<const R*>(L.adj_halo[3]);
+            k_adj_step<FORM, COLL, VAR, GM, FROZEN, RPT, true>
+                <<<dim3(static_cast<unsigned>(nb)), dim3(256), 0, L.stream>>>(
+                    static_cast<const S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx, L.ny,
+                    L.pitch, ntx, nty, make_coef<R>(L), out, sh, lh);
+            return;
+        }
         if (!fsrc) {
-            k_adj_step<FORM, COLL, VAR, GM, FROZEN, RPT><<<dim3(static_cast<unsigned>(nb)), dim3(256), 0, L.stream>>>(
-                static_cast<const S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx, L.ny, L.pitch,
-                ntx, nty, make_coef<R>(L), out);
+            k_adj_step<FORM, COLL, VAR, GM, FROZEN, RPT, false>
+                <<<dim3(static_cast<unsigned>(nb)), dim3(256), 0, L.stream>>>(
+                    static_cast<const S*>(state), static_cast<const R*>(lin), static_cast<R*>(lout), L.nx, L.ny,
+                    L.pitch, ntx, nty, make_coef<R>(L), out, SlabHalo<S>{}, SlabHalo<R>{});
             return;
         }
         // forward part: 256 x 1 tiles, renumbered per XCD as in the step kernel
@@ -377,6 +410,7 @@ struct AdjStepOp {
         const int64_t nb = adj_blocks(L);
         if (static_cast<int64_t>(ntx) * nty > (int64_t{1} << 30) || nb > (int64_t{1} << 31) - 1) return -1;
         if ((fsrc == nullptr) != (fdst == nullptr)) return -1;
+        if (L.adj_halo[0] && fsrc) return -1;   // a slab's adjoint step runs alone
         // the fused forward part needs its grid to fit next to the adjoint's
         if (fsrc && (static_cast<int64_t>((L.nx + 255) / 256) * L.ny + 8 + nb > (int64_t{1} << 31) - 1)) return -1;
         const bool direct = nb <= kDirect;

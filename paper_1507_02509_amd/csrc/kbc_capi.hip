@@ -542,6 +542,23 @@ int lbm_adjoint_seed(lbm_ctx* c, const void* state, const double* dL_drho, const
     return launch_result(kbc::launch_adjoint_seed(c->L, state, dL_drho, dL_dux, dL_duy, lam), "lbm_adjoint_seed");
 }
 
+int lbm_adjoint_step_slab(lbm_ctx* c, const void* state, const void* state_lo, const void* state_hi,
+                          const void* lam_in, const void* lam_lo, const void* lam_hi, void* lam_out, double* dbeta) {
+    if (!c || !state || !lam_in || !lam_out || lam_in == lam_out)
+        return fail(LBM_EINVAL, "ctx, state and two distinct adjoint buffers are required");
+    if (!state_lo || !state_hi || !lam_lo || !lam_hi) return fail(LBM_EINVAL, "all four halo buffers are required");
+    kbc::Lattice L = c->L;
+    L.adj_halo[0] = state_lo;
+    L.adj_halo[1] = state_hi;
+    L.adj_halo[2] = lam_lo;
+    L.adj_halo[3] = lam_hi;
+    const int64_t nb = kbc::adjoint_partials(L), ng = kbc::adjoint_slice_len(L);
+    int rc = ensure_ascratch(c, static_cast<size_t>(nb + ng));
+    if (rc) return rc;
+    return launch_result(kbc::launch_adjoint_step(L, state, lam_in, lam_out, c->ascratch, c->ascratch + nb, dbeta),
+                         "lbm_adjoint_step_slab");
+}
+
 int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out, double* dbeta) {
     if (!c || !state || !lam_in || !lam_out || lam_in == lam_out)
         return fail(LBM_EINVAL, "ctx, state and two distinct adjoint buffers are required");

@@ -21,6 +21,10 @@ struct Lattice {
     // periodic lattice.  Only the step launches read them.
     const void* halo_lo = nullptr;
     const void* halo_hi = nullptr;
+    // adjoint step of a slab: the same two-row halos of the state f^n (lo,
+    // hi) and of the incoming adjoint lambda^(n+1) (lo, hi; [2][9][pitch] of
+    // the adjoint type); null for a periodic lattice
+    const void* adj_halo[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 // step kernel tile: `width` in {64, 128, 256} nodes, each thread walks `rpt`

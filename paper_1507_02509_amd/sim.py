@@ -250,6 +250,14 @@ class Sim:
         L.check(self.lib.lbm_adjoint_step(self.ctx, L.ptr(state), L.ptr(lam_in), L.ptr(lam_out), L.ptr(dbeta)),
                 "lbm_adjoint_step")
 
+    def adjoint_step_slab(self, state, state_lo, state_hi, lam_in, lam_lo, lam_hi, lam_out, dbeta=None):
+        """The adjoint step of a slab (lbm_adjoint_step_slab): rows -2, -1 and
+        ny, ny + 1 of the state and of lam_in from the given [2, 9, pitch]
+        halo tensors."""
+        L.check(self.lib.lbm_adjoint_step_slab(self.ctx, L.ptr(state), L.ptr(state_lo), L.ptr(state_hi),
+                                               L.ptr(lam_in), L.ptr(lam_lo), L.ptr(lam_hi), L.ptr(lam_out),
+                                               L.ptr(dbeta)), "lbm_adjoint_step_slab")
+
     def adjoint_step_noalloc(self, state, lam_in, lam_out, dbeta=None):
         """lbm_adjoint_step_noalloc: the same step with the library's fixed
         per-GPU scratch array (allocates nothing; overlapping calls on one

@@ -126,3 +126,45 @@ def test_slab_rules():
     periodic.state_buffer().copy_(full.state_buffer()[:16])
     periodic.step(3)
     assert torch.equal(s.state_buffer()[:, :, :64], periodic.state_buffer()[:, :, :64])
+
+
+def two_rows(t, r0, ny):
+    """Rows r0 and r0 + 1 (periodic in the domain) of a [ny, 9, pitch] field."""
+    return torch.stack([t[r0 % ny], t[(r0 + 1) % ny]]).contiguous()
+
+
+@pytest.mark.parametrize("form", ["f32", "f64", "f16"])
+@pytest.mark.parametrize("coll,var", [("kbc", "B"), ("lbgk", "A"), ("kbc", "D")])
+def test_slab_adjoint_step_equals_domain(form, coll, var):
+    """The adjoint step of each slab (lbm_adjoint_step_slab), with the state's
+    and the incoming adjoint's rows beyond the slab taken from the
+    neighbouring slabs, equals the whole domain's adjoint step on those rows
+    bit for bit; the slabs' dL/dbeta shares add up to the domain's."""
+    nx, heights = 100, (13, 20, 7)
+    ny = sum(heights)
+    say("slab adjoint", form, coll, var)
+    beta = beta_from_nu(1e-3)
+    ux, uy = inputs.spectral(nx, 3, 0.05, seed=33, ny=ny)
+    full = Sim(nx, ny, beta, collision=coll, variant=var, form=form).init(ux, uy)
+    full.step(3)
+    state = full.state_buffer()
+    lin = full.new_adjoint()
+    g = torch.Generator(device="cuda").manual_seed(34)
+    lin.copy_(torch.randn(lin.shape, generator=g, device="cuda", dtype=torch.float64).to(lin.dtype))
+    lout = full.new_adjoint().zero_()
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    full.adjoint_step(state, lin, lout, acc)
+    y, total = 0, 0.0
+    for h in heights:
+        s = Sim(nx, h, beta, collision=coll, variant=var, form=form)
+        s.init(np.zeros((h, nx)), np.zeros((h, nx)), mode="eq")
+        st = state[y:y + h].contiguous()
+        li = lin[y:y + h].contiguous()
+        out = s.new_adjoint().zero_()
+        a = torch.zeros(1, dtype=torch.float64, device="cuda")
+        s.adjoint_step_slab(st, two_rows(state, y - 2, ny), two_rows(state, y + h, ny), li,
+                            two_rows(lin, y - 2, ny), two_rows(lin, y + h, ny), out, a)
+        assert torch.equal(out[:, :, :nx], lout[y:y + h, :, :nx])
+        total += a.item()
+        y += h
+    assert total == pytest.approx(acc.item(), rel=1e-9, abs=1e-12)
