@@ -94,6 +94,7 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.lbm_set_graph(None, 8) == L.LBM_EINVAL
     assert lib.lbm_set_halo(None, None, None) == L.LBM_EINVAL
     assert lib.lbm_get_edge_rows(None, None, None) == L.LBM_EINVAL
+    assert lib.lbm_adjoint_step_slab(None, None, None, None, None, None, None, None, None) == L.LBM_EINVAL
     assert lib.lbm_get_graph(None) == -1
     assert lib.lbm_step_count(None) == -1
     assert lib.lbm_free(None) == L.LBM_OK
