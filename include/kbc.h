@@ -91,7 +91,7 @@ typedef enum { LBM_GAMMA_ESTIMATE = 0, LBM_GAMMA_FIXED = 1, LBM_GAMMA_EXACT = 2 
 typedef enum { LBM_INIT_EQ = 0, LBM_INIT_GRAD_CD = 1, LBM_INIT_GRAD_GIVEN = 2 } lbm_init_mode;
 
 typedef struct {
-    int32_t nx, ny;        /* lattice size, each >= 3 */
+    int32_t nx, ny;        /* lattice size, each in [3, 2^28] (see "Size limits") */
     double beta;           /* relaxation parameter, 0 < beta <= 1 */
     double rho0;           /* reference density of the deviation storage (> 0, usually 1) */
     int32_t collision;     /* lbm_collision */
@@ -120,8 +120,22 @@ typedef struct {
     double reserved;
 } lbm_diag;
 
+/* Size limits.  Each side is at most 2^28 nodes, so that a node's byte
+ * offset within a population row is a 32-bit value.  A kernel launch holds at
+ * most 2^32 - 1 work-items (the grid size of a dispatch is 32-bit); a call
+ * whose launch would need more returns LBM_EUNSUPPORTED and enqueues nothing.
+ * Work-items per node: 1 / rows-per-thread for the single step (1/4 with the
+ * FP16 default 256 x 4 tile, 1 with the FP32 and FP64 defaults), 4 / rows for
+ * the fused step (1/4 with 16-row tiles, 1/2 with FP64's 8), 1 / (rows per
+ * thread) for the adjoint step (1/2 for FP32 and FP16 lattices of at least
+ * 8192 tiles of 128 x 4 nodes, else 1), plus 1 for the forward step that
+ * lbm_adjoint_rollout combines with it, and 1 for lbm_adjoint_init.  So every
+ * lattice whose buffers fit the device's memory steps in the default
+ * configuration (the largest: about 2^32 nodes in FP16, two 77 GB population
+ * buffers).  Offsets of rows within buffers are 64-bit everywhere. */
+
 /* Smallest legal pitch (elements) for nx in form f: nx rounded up to 64.
- * Returns 0 for invalid arguments. */
+ * Returns 0 for invalid arguments (nx outside [1, 2^28], unknown form). */
 size_t lbm_required_pitch(int32_t nx, int32_t form);
 
 /* Bytes of one population buffer: 9 * ny * pitch * sizeof(storage type). */

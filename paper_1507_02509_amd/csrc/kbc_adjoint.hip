@@ -408,11 +408,11 @@ struct AdjStepOp {
         const int rpt = adj_rows_per_thread(L);
         const int ntx = (L.nx + 127) / 128, nty = (L.ny + 2 * rpt - 1) / (2 * rpt);
         const int64_t nb = adj_blocks(L);
-        if (static_cast<int64_t>(ntx) * nty > (int64_t{1} << 30) || nb > (int64_t{1} << 31) - 1) return -1;
+        if (!grid_fits(nb, 256)) return kTooLarge;
         if ((fsrc == nullptr) != (fdst == nullptr)) return -1;
         if (L.adj_halo[0] && fsrc) return -1;   // a slab's adjoint step runs alone
         // the fused forward part needs its grid to fit next to the adjoint's
-        if (fsrc && (static_cast<int64_t>((L.nx + 255) / 256) * L.ny + 8 + nb > (int64_t{1} << 31) - 1)) return -1;
+        if (fsrc && !grid_fits(static_cast<int64_t>((L.nx + 255) / 256) * L.ny + 8 + nb, 256)) return kTooLarge;
         const bool direct = nb <= kDirect;
         if (!slice || (!direct && !partials)) return -1;
         double* out = direct ? slice : partials;
@@ -502,7 +502,8 @@ int launch_adjoint_init(const Lattice& L, const double* rho, const double* ux, c
                         int64_t nblocks_cap, double* acc) {
     const int64_t N = static_cast<int64_t>(L.nx) * L.ny;
     const int64_t nb = (N + 255) / 256;
-    if (nb > nblocks_cap || nb > (int64_t{1} << 31) - 1) return -1;
+    if (!grid_fits(nb, 256)) return kTooLarge;
+    if (nb > nblocks_cap) return -1;
     const dim3 g(static_cast<unsigned>(nb)), b(256);
     if (L.form == F64)
         k_adj_init_a<double><<<g, b, 0, L.stream>>>(static_cast<const double*>(lam0), L.nx, L.ny, L.pitch, L.rho0, L.beta, rho, ux, uy, mode, gux, guy, P, partials);

@@ -368,7 +368,7 @@ int launch_copy(void* dst, const void* src, size_t n_words, hipStream_t stream) 
     const int64_t n = static_cast<int64_t>(n_words);
     if (n == 0) return 0;
     const int64_t blocks = (n + 255) / 256;
-    if (blocks > (int64_t{1} << 31) - 1) return -1;
+    if (!grid_fits(blocks, 256)) return kTooLarge;
     k_copy<<<static_cast<unsigned>(blocks), 256, 0, stream>>>(static_cast<float*>(dst), static_cast<const float*>(src), n);
     return ok_launch();
 }

@@ -62,6 +62,8 @@ int launch_result(int rc, const char* what) {
     if (rc == 0) return LBM_OK;
     if (rc == -1) return fail(LBM_EINVAL, "%s: invalid configuration", what);
     if (rc == -5) return fail(LBM_EUNSUPPORTED, "%s: combination not built", what);
+    if (rc == kbc::kTooLarge)
+        return fail(LBM_EUNSUPPORTED, "%s: lattice too large for one launch (2^32 - 1 work-items)", what);
     return fail(LBM_EHIP, "%s: kernel launch failed: %s", what, hipGetErrorString(hipGetLastError()));
 }
 
@@ -77,6 +79,8 @@ size_t form_bytes(int32_t form) {
 int check_params(const lbm_params* p) {
     if (!p) return fail(LBM_EINVAL, "params is NULL");
     if (p->nx < 3 || p->ny < 3) return fail(LBM_EINVAL, "nx, ny must be >= 3 (got %d x %d)", p->nx, p->ny);
+    if (p->nx > kbc::kMaxSide || p->ny > kbc::kMaxSide)
+        return fail(LBM_EINVAL, "nx, ny must be <= 2^28 (got %d x %d)", p->nx, p->ny);
     if (!(p->beta > 0.0 && p->beta <= 1.0)) return fail(LBM_EINVAL, "beta must be in (0, 1] (got %g)", p->beta);
     if (!(p->rho0 > 0.0) || !isfinite(p->rho0)) return fail(LBM_EINVAL, "rho0 must be > 0");
     if (p->collision != LBM_LBGK && p->collision != LBM_KBC) return fail(LBM_EINVAL, "unknown collision %d", p->collision);
@@ -126,7 +130,7 @@ extern "C" {
 const char* lbm_last_error(void) { return g_err; }
 
 size_t lbm_required_pitch(int32_t nx, int32_t form) {
-    if (nx < 1 || form_bytes(form) == 0) return 0;
+    if (nx < 1 || nx > kbc::kMaxSide || form_bytes(form) == 0) return 0;
     return (static_cast<size_t>(nx) + 63) / 64 * 64;
 }
 
@@ -785,7 +789,7 @@ int64_t ens_table(const lbm_ens* e, int tw, int th, std::vector<kbc::EnsEntry>& 
         t.pitch = c->L.pitch;
         t.tile_start = static_cast<int32_t>(tiles);
         tiles += static_cast<int64_t>(t.ntx) * ((c->p.ny + th - 1) / th);
-        if (tiles > (int64_t{1} << 30)) return -1;
+        if (!kbc::grid_fits(8 * ((tiles + 7) / 8), 256)) return -1;
         t.beta = c->L.beta;
         t.inv_beta = 1.0 / c->L.beta;
         t.two_m_inv_beta = 2.0 - 1.0 / c->L.beta;
@@ -841,7 +845,8 @@ int ens_build(lbm_ens* e) {
     std::vector<kbc::EnsEntry> tab;
     const int64_t tiles = ens_table(e, e->shape.width, (256 / e->shape.width) * e->shape.rpt, tab);
     const int64_t tiles2 = tiles < 0 ? -1 : ens_table(e, 64, e->rows, tab);
-    if (tiles < 0 || tiles2 < 0) return fail(LBM_EINVAL, "ensemble has too many tiles");
+    if (tiles < 0 || tiles2 < 0)
+        return fail(LBM_EUNSUPPORTED, "ensemble has too many tiles for one launch (2^32 - 1 work-items)");
     int rc = ens_upload(e, &e->dtab2, tab);
     if (rc) return rc;
     e->ntiles2 = static_cast<int>(tiles2);

@@ -8,6 +8,18 @@
 
 namespace kbc {
 
+// Largest lattice side: a lane's byte offset within a population row (x times
+// the element size, at most 8 bytes) stays a 32-bit value.
+constexpr int32_t kMaxSide = 1 << 28;
+
+// A dispatch's grid size is a 32-bit count of work-items, so one launch holds
+// at most 2^32 - 1 of them.  Launch helpers return kTooLarge when a lattice
+// would need more.
+constexpr int kTooLarge = -6;
+inline bool grid_fits(int64_t blocks, int64_t threads_per_block) {
+    return blocks >= 1 && blocks <= (int64_t{0xffffffff} / threads_per_block);
+}
+
 // Everything a kernel launch needs about one lattice.
 struct Lattice {
     int nx, ny;

@@ -52,7 +52,7 @@ struct StepOp {
         const int ntx = (L.nx + TW - 1) / TW;
         const int nty = (L.ny + TH - 1) / TH;
         const int64_t ntiles64 = static_cast<int64_t>(ntx) * nty;
-        if (ntiles64 > (int64_t{1} << 30)) return -1;
+        if (!grid_fits(8 * ((ntiles64 + 7) / 8), 256)) return kTooLarge;
         const int ntiles = static_cast<int>(ntiles64);
         const int per_xcd = (ntiles + 7) / 8;
         SlabHalo<S> halo;

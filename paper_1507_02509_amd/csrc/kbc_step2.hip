@@ -27,7 +27,8 @@ static_assert(kPanel > 0 && (kPanel & (kPanel - 1)) == 0, "panel width must be a
 // Tile (tx, ty) of panel-order index u: full panels of kPanel columns, then
 // one panel of the remaining `last` columns (0 if ntx is a multiple).
 // (With no full panel the order is row-major; otherwise kPanel * nty is at
-// most the tile count, which the host keeps below 2^30.)
+// most the tile count, which the host keeps below 2^24: a launch holds at
+// most 2^32 - 1 work-items.)
 __device__ __forceinline__ void panel_tile(int u, int ntx, int nty, int& tx, int& ty) {
     const int full = ntx / kPanel;
     if (full == 0) {
@@ -72,7 +73,7 @@ struct Step2Op {
         const int ntx = (L.nx + 63) / 64;
         const int nty = (L.ny + TH - 1) / TH;
         const int64_t ntiles64 = static_cast<int64_t>(ntx) * nty;
-        if (ntiles64 > (int64_t{1} << 30)) return -1;
+        if (!grid_fits(8 * ((ntiles64 + 7) / 8), 256)) return kTooLarge;
         const int ntiles = static_cast<int>(ntiles64);
         const int per_xcd = (ntiles + 7) / 8;
         SlabHalo<S> halo;

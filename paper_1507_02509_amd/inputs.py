@@ -21,6 +21,8 @@ Workloads:
     N > 2 K + 1.
   * ``shear_layer`` -- the doubly periodic shear layer with its tanh profile
     and sinusoidal perturbation.
+  * ``uniform_noise`` -- independent uniform velocity at every node, drawn on
+    the device: the field for lattices too large for a spectral synthesis.
 """
 from __future__ import annotations
 
@@ -122,6 +124,20 @@ def spectral(n: int, k0: float, u_rms: float, seed: int, kind: str = "gauss4",
         raise ValueError("degenerate spectral field")
     s = u_rms / rms
     return ux.mul_(s), uy.mul_(s)
+
+
+def uniform_noise(nx: int, ny: int, amp: float, seed: int, device):
+    """u_x and u_y drawn independently and uniformly from [-amp, amp] at every
+    node by torch's seeded generator on `device`, as float64 tensors [ny, nx]
+    (the same numbers on every run with the same seed and device type).  The
+    field has no smoothness: every node's velocity, and so its populations,
+    differ from its neighbours', which makes any misplaced row or column of a
+    lattice show."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(int(seed))
+    ux = torch.empty((ny, nx), dtype=torch.float64, device=device).uniform_(-amp, amp, generator=g)
+    uy = torch.empty((ny, nx), dtype=torch.float64, device=device).uniform_(-amp, amp, generator=g)
+    return ux, uy
 
 
 def shear_layer(n: int, u0: float = 0.04, kappa: float = 80.0, delta: float = 0.05):

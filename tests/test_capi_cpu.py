@@ -35,6 +35,11 @@ def test_pitch_and_bytes(lib):
     assert lib.lbm_buffer_bytes(100, 10, L.F32DEV_F32) == 9 * 10 * 128 * 4
     assert lib.lbm_buffer_bytes(100, 10, L.F16DEV_F32) == 9 * 10 * 128 * 2
     assert lib.lbm_buffer_bytes(100, 10, L.F64) == 9 * 10 * 128 * 8
+    # sides are at most 2^28 nodes (32-bit byte offsets within a row)
+    assert lib.lbm_required_pitch(1 << 28, L.F64) == 1 << 28
+    assert lib.lbm_required_pitch((1 << 28) + 1, L.F16DEV_F32) == 0
+    assert lib.lbm_buffer_bytes((1 << 28) + 1, 3, L.F32DEV_F32) == 0
+    assert lib.lbm_buffer_bytes(65536, 65536, L.F16DEV_F32) == 9 * 65536 * 65536 * 2
 
 
 def _params(**kw):
@@ -54,6 +59,8 @@ A, B, U, V, G = 0x100000, 0x200000, 0x300000, 0x400000, 0x500000
 @pytest.mark.parametrize("kw,args,code", [
     (dict(nx=2), {}, L.LBM_EINVAL),
     (dict(ny=1), {}, L.LBM_EINVAL),
+    (dict(nx=(1 << 28) + 1), {}, L.LBM_EINVAL),
+    (dict(ny=(1 << 28) + 1), {}, L.LBM_EINVAL),
     (dict(beta=0.0), {}, L.LBM_EINVAL),
     (dict(beta=1.5), {}, L.LBM_EINVAL),
     (dict(beta=float("nan")), {}, L.LBM_EINVAL),
