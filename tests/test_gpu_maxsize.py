@@ -157,3 +157,46 @@ def test_lattice_at_memory_limit(orc, form, n):
     s.free()
     del s, ux, uy
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 300000), (1048579, 3)])
+def test_extreme_aspect_ratios(orc, nx, ny):
+    """A tall lattice (300000 rows: the node kernels' grids run 75000
+    workgroups in y) and a wide one (2^20 + 3 columns, the minimum 3 rows),
+    FP32 KBC-B: one single step and two fused, sampled against oracle
+    windows; then the moments (lbm_moments) at the same nodes against the
+    oracle's moments of its window."""
+    form = "f32"
+    say(f"aspect {nx} x {ny}")
+    beta = beta_from_nu(NU)
+    ux, uy = inputs.uniform_noise(nx, ny, AMP, SEED, "cuda")
+    s = Sim(nx, ny, beta, collision="kbc", variant="B", form=form, fusion=(1, 0)).init(ux, uy)
+    rows = sorted({0, 1, 2, ny // 2, ny - 2, ny - 1, min(ny - 1, 4 * 65536), min(ny - 1, 4 * 65536 + 3)})
+    cols = sorted(c for c in {0, 1, 63, 64, nx // 2, nx - 2, nx - 1} if c < nx)
+    pts = [(x, y) for y in rows for x in cols]
+    s.step(1)
+    torch.cuda.synchronize()
+    check(orc, s, form, ux, uy, beta, pts, 1, TOL1[form])
+    s.set_fusion(2)
+    s.step(2)
+    torch.cuda.synchronize()
+    check(orc, s, form, ux, uy, beta, pts, 3, TOL3[form])
+    rho, mx, my = s.moments()
+    xs = torch.as_tensor([p[0] for p in pts], device="cuda")
+    ys = torch.as_tensor([p[1] for p in pts], device="cuda")
+    got = np.stack([t[ys, xs].cpu().numpy() for t in (rho, mx, my)], axis=1)
+    want = []
+    for x, y in pts:
+        h = 5
+        d = np.arange(-h, h + 1)
+        iy = torch.as_tensor((y + d) % ny, device="cuda")[:, None]
+        ix = torch.as_tensor((x + d) % nx, device="cuda")[None, :]
+        p = orc.Params(2 * h + 1, 2 * h + 1, beta, collision=orc.KBC, variant=orc.VARIANTS["B"])
+        f = orc.run(p, orc.init(p, ux[iy, ix].cpu().numpy(), uy[iy, ix].cpu().numpy()), 3)
+        r, u, v = orc.moments(p, f)
+        want.append([r[h, h], u[h, h], v[h, h]])
+    want = np.array(want)
+    err_rho = np.abs(got[:, 0] - want[:, 0]).max()
+    err_u = np.abs(got[:, 1:] - want[:, 1:]).max() / np.abs(want[:, 1:]).max()
+    say(f"  moments after 3 steps: |drho| {err_rho:.2e}, u relative {err_u:.2e}")
+    assert err_rho < 1e-6 and err_u < 1e-4
