@@ -53,6 +53,9 @@ STEP_SOURCES = [os.path.join(_CSRC, f)
 FLOPS_PER_NODE_STEP = {"f32": 266, "f16": 302, "f64": 382}
 VECTOR_PEAK_TFLOPS = {"f32": 157.3, "f16": 157.3, "f64": 78.6}
 VALU_ISSUE_PEAK = 256 * 64 * 2.4e9   # lane-instructions/s: 256 CUs, 64 lanes, nominal clock
+# untimed steps before each extra measurement, so that none is timed while the
+# clock is still ramping up after the previous one's host-side work
+EXTRA_WARMUP = 20
 ADJOINT_SOURCES = [os.path.join(_CSRC, f)
                    for f in ("kbc_adjoint.hip", "kbc_adjoint.hpp", "kbc_tile.hpp", "kbc_device.hpp")]
 
@@ -120,7 +123,7 @@ def time_adjoint(n, nu, seed, k0, dev, steps=20):
     la.normal_()
     acc = torch.zeros(1, dtype=torch.float64, device=dev)
     state = sim.state_buffer()
-    for _ in range(2):
+    for _ in range(EXTRA_WARMUP):
         sim.adjoint_step(state, la, lb, acc)
         la, lb = lb, la
     torch.cuda.synchronize()
@@ -182,7 +185,7 @@ def time_c5(dev):
     return out
 
 
-def time_slab(dev, steps=50, slabs=8):
+def time_slab(dev, steps=200, slabs=8):
     """One GPU's share of the 16384^2 workload split in y over `slabs` GPUs:
     a 16384 x (16384 / slabs) slab whose rows -2, -1 and ny, ny + 1 come
     from halo buffers (lbm_set_halo).  Before every launch of two fused steps
@@ -214,16 +217,20 @@ def time_slab(dev, steps=50, slabs=8):
             s.step(2)
         if mode == "halo":
             s.set_halo(lo, hi)
-        for _ in range(5):
+        # 100 warm-up steps: after 10 this slab measured 117.6 G node-steps/s,
+        # after 200 (in another run) 141.6, the clock's ramp after the
+        # previous benchmark's host-side work
+        for _ in range(50):
             launch()
         torch.cuda.synchronize()
+        launches = max(steps, 200) // 2
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(steps // 2):
+        for _ in range(launches):
             launch()
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / (2 * (steps // 2))
+        ms = e0.elapsed_time(e1) / (2 * launches)
         res[mode] = {"ms_per_step": round(ms, 4), "mlups": round(n * h / (ms * 1e-3) / 1e6, 1)}
         del s
         torch.cuda.empty_cache()
@@ -355,7 +362,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--form", default="f32", choices=["f16", "f32", "f64"])
     ap.add_argument("--variant", default="B")
@@ -441,7 +448,7 @@ def main():
                 continue
             s = make_sim(n, form, "kbc", args.variant, nu, seed, k0, dev)
             fs = s.fusion
-            m, _ = time_steps(s, args.extra_steps, 2)
+            m, _ = time_steps(s, args.extra_steps, EXTRA_WARMUP)
             progress(f"{form}: {m:.4f} ms/step")
             del s
             torch.cuda.empty_cache()
@@ -458,7 +465,7 @@ def main():
                 gamma_mode="exact", device=dev).init(ux, uy)
         del ux, uy
         fs = s.fusion
-        m, _ = time_steps(s, args.extra_steps, 2)
+        m, _ = time_steps(s, args.extra_steps, EXTRA_WARMUP)
         progress(f"exact stabiliser: {m:.4f} ms/step")
         d = s.diagnostics()
         del s
@@ -469,7 +476,7 @@ def main():
     if "lbgk" in want:
         s = make_sim(n, args.form, "lbgk", "A", nu, seed, k0, dev)
         fs = s.fusion
-        m, _ = time_steps(s, args.extra_steps, 2)
+        m, _ = time_steps(s, args.extra_steps, EXTRA_WARMUP)
         del s
         torch.cuda.empty_cache()
         extras[f"lbgk_{args.form}"] = {"mlups": round(nodes / (m * 1e-3) / 1e6, 1), "ms_per_step": round(m, 4),
