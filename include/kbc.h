@@ -123,7 +123,9 @@ typedef struct {
 /* Size limits.  Each side is at most 2^28 nodes, so that a node's byte
  * offset within a population row is a 32-bit value.  A kernel launch holds at
  * most 2^32 - 1 work-items (the grid size of a dispatch is 32-bit); a call
- * whose launch would need more returns LBM_EUNSUPPORTED and enqueues nothing.
+ * whose launch would need more returns LBM_EUNSUPPORTED without making that
+ * launch (every launch of lbm_step has the same grid, so it enqueues
+ * nothing; lbm_adjoint_rollout may have enqueued earlier, smaller ones).
  * Work-items per node: 1 / rows-per-thread for the single step (1/4 with the
  * FP16 default 256 x 4 tile, 1 with the FP32 and FP64 defaults), 4 / rows for
  * the fused step (1/4 with 16-row tiles, 1/2 with FP64's 8), 1 / (rows per
