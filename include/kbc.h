@@ -200,10 +200,12 @@ void* lbm_work_buffer(const lbm_ctx* c);
 
 /* Workgroup tile of the step kernel: `width` in {64, 128, 256} nodes by
  * (256 / width) * rows_per_thread rows, rows_per_thread in {1, 2, 4}
- * (default per form, all non-temporal: 256 x 4 for FP16, 256 x 1 for FP32,
- * 128 x 2 for FP64); flags: LBM_TILE_NONTEMPORAL writes the new state with
- * non-temporal stores.  A tuning knob only: results are bitwise identical for
- * every setting. */
+ * (default per form: 256 x 4 for FP16, 256 x 1 for FP32, 128 x 2 for FP64);
+ * flags: LBM_TILE_NONTEMPORAL writes the new state with non-temporal stores
+ * (by default on, except for lattices whose two buffers together take between
+ * 40 MB (80 MB for FP16) and 256 MiB: the last-level cache then holds the new
+ * state for the next step).  The flag applies to the fused launch too.  A
+ * tuning knob only: results are bitwise identical for every setting. */
 #define LBM_TILE_NONTEMPORAL 1
 int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t flags);
 

@@ -307,6 +307,28 @@ def test_fused_panel_order_bitwise(form):
         assert torch.equal(o, outs[0])
 
 
+@pytest.mark.parametrize("form,n", [("f32", 1024), ("f64", 1024), ("f16", 1536), ("f32", 640)])
+def test_store_kind_bitwise(form, n):
+    """The default store kind depends on the lattice's footprint (plain
+    stores where the two buffers fit the last-level cache, non-temporal
+    otherwise); both kinds give the same state bit for bit, fused and single
+    step."""
+    say("store kind", form, n)
+    ux, uy = inputs.spectral(n, 8, 0.05, seed=24, device="cuda")
+    default_tile = {"f32": (256, 1), "f16": (256, 4), "f64": (128, 1)}[form]
+    outs = []
+    for fusion in ((2, 0), (1, 0)):
+        for nt in (None, True, False):
+            s = Sim(n, n, beta_from_nu(1e-4), collision="kbc", variant="B", form=form, fusion=fusion)
+            s.init(ux, uy)
+            if nt is not None:
+                s.set_tile(*default_tile, nontemporal=nt)
+            s.step(5)
+            outs.append(s.state_buffer()[:, :, :n].clone())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_diagnostics_parity(orc, form):
     nx, ny = 67, 45
