@@ -215,7 +215,7 @@ int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t fla
  * steps reads and writes the state once).  `rows` in {8, 16, 24, 32} sets the
  * fused tile height (0 keeps the current one; 32 is LBM_EUNSUPPORTED for
  * FP64, whose tile would not fit the LDS of a CU).  Defaults: 2 steps with 16
- * rows for FP32 and FP16 (8 rows when the lattice has fewer than 1024 tiles
+ * rows for FP32 and FP16 (8 rows when the lattice has fewer than 1792 tiles
  * of 16 rows), 8 rows for FP64.  Odd
  * remainders run as single steps.  Results are bitwise identical for every
  * setting; the non-temporal flag of lbm_set_tile applies to the fused launch

@@ -186,9 +186,11 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     // the ring of extra step-1 collisions costs less than the HBM pass it saves)
     c->fuse = 2;
     c->fuse_rows = (p->form == LBM_F64) ? 8 : 16;
-    // small lattices: fewer than 1024 tiles of 16 rows leave most CUs with one
-    // workgroup; 8-row tiles double the count (512^2: 3.9 vs 4.5 us per step)
-    if (static_cast<int64_t>((p->nx + 63) / 64) * ((p->ny + 15) / 16) < 1024) c->fuse_rows = 8;
+    // smaller lattices: 8-row tiles double the workgroup count, which pays
+    // below about 1792 tiles of 16 rows (FP32, us per step with 8 / 16 rows:
+    // 512^2 3.7 / 4.2, 1152^2 11.5 / 12.1, 1280^2 13.5 / 14.1, 1408^2 a tie;
+    // FP16 alike)
+    if (static_cast<int64_t>((p->nx + 63) / 64) * ((p->ny + 15) / 16) < 1792) c->fuse_rows = 8;
     c->dscratch = nullptr;
     c->dscratch_elems = 0;
     c->ascratch = nullptr;
