@@ -412,7 +412,9 @@ typedef struct lbm_ens lbm_ens;
 int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count);
 
 /* Tile of the ensemble kernel: 128 x 4 (width 128, 2 rows per thread),
- * 256 x 1 or 256 x 2; flags as for lbm_set_tile.  Synchronises the stream. */
+ * 256 x 1 or 256 x 2; flags as for lbm_set_tile (the default store kind
+ * follows the same rule, applied to all members' buffers together).
+ * Synchronises the stream. */
 int lbm_ensemble_set_tile(lbm_ens* e, int32_t width, int32_t rows_per_thread, int32_t flags);
 
 /* Steps per launch of lbm_ensemble_step: 1, or 2 (the fused two-step tile of

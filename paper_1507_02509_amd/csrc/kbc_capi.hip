@@ -93,6 +93,20 @@ int check_params(const lbm_params* p) {
     return LBM_OK;
 }
 
+// Whether the state should be written with plain rather than non-temporal
+// stores, given the bytes of all state buffers a step reads and writes:
+// plain where they outgrow the L2s but fit the 256 MiB last-level cache,
+// which then still holds the new state when the next step reads it.
+// Measured on MI355X (KBC-B, default tiles, fused steps): FP32 1024^2 8.97
+// against 11.14 us per step, 1792^2 23.2 against 27.3; FP64 1024^2 15.8
+// against 18.1; below the lower bound (FP32 640^2, FP64 512^2) and above
+// 256 MiB (FP32 2048^2, FP64 1536^2) non-temporal stores were 1-10 % faster.
+// FP16, bound by vector issue, gains least and only from 80 MB on.
+bool plain_stores_pay(int32_t form, double state_bytes) {
+    const double lo = (form == LBM_F16DEV_F32) ? 80e6 : 40e6;
+    return state_bytes >= lo && state_bytes <= 256.0 * 1024.0 * 1024.0;
+}
+
 // Default step tile per storage form, from a sweep on MI355X at 16384^2
 // (the autotuner in the Python package can replace it per lattice).
 kbc::StepShape default_shape(int32_t form) {
@@ -168,19 +182,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, size_
     c->cur = 0;
     c->steps = 0;
     c->shape = default_shape(p->form);
-    // Plain stores where the two buffers outgrow the L2s but fit the 256 MiB
-    // last-level cache, which then still holds the new state when the next
-    // step reads it; non-temporal stores otherwise.  Measured on MI355X (KBC-B,
-    // default tiles, fused steps): FP32 1024^2 8.97 against 11.14 us per step,
-    // 1792^2 23.2 against 27.3; FP64 1024^2 15.8 against 18.1; below the lower
-    // bound (FP32 640^2, FP64 512^2) and above 256 MiB (FP32 2048^2, FP64
-    // 1536^2) non-temporal stores were 1-10 % faster.  FP16, bound by vector
-    // issue, gains least and only from 80 MB on.
-    {
-        const double both = 2.0 * static_cast<double>(bytes);
-        const double lo = (p->form == LBM_F16DEV_F32) ? 80e6 : 40e6;
-        if (both >= lo && both <= 256.0 * 1024.0 * 1024.0) c->shape.nt = 0;
-    }
+    if (plain_stores_pay(p->form, 2.0 * static_cast<double>(bytes))) c->shape.nt = 0;
     // two fused steps per launch by default for every form (measured for
     // KBC-B at 16384^2: FP32 +38 %, FP64 +25 %, FP16 +6 % over single steps;
     // the ring of extra step-1 collisions costs less than the HBM pass it saves)
@@ -931,6 +933,13 @@ int lbm_ensemble_create(lbm_ens** out, lbm_ctx* const* members, int32_t count) {
     if (!ens_shape_ok(e->shape)) {
         e->shape.width = 128;
         e->shape.rpt = 2;
+    }
+    {
+        // every member's two buffers pass through each launch
+        double state = 0.0;
+        for (const lbm_ctx* c : e->m)
+            state += 2.0 * 9.0 * c->p.ny * static_cast<double>(c->L.pitch) * form_bytes(c->p.form);
+        if (plain_stores_pay(m0->p.form, state)) e->shape.nt = 0;
     }
     e->dtab = nullptr;
     e->dtab2 = nullptr;
