@@ -208,6 +208,9 @@ void* lbm_work_buffer(const lbm_ctx* c);
  * tuning knob only: results are bitwise identical for every setting. */
 #define LBM_TILE_NONTEMPORAL 1
 int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t flags);
+/* The current tile and flags (any pointer may be NULL); LBM_EINVAL for a
+ * NULL ctx. */
+int lbm_get_tile(const lbm_ctx* c, int32_t* width, int32_t* rows_per_thread, int32_t* flags);
 
 /* Time steps per kernel launch in lbm_step: 1, or 2 (temporal blocking: each
  * workgroup runs the first step on its 64 x `rows` tile plus a one-node ring,

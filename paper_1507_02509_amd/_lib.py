@@ -65,6 +65,7 @@ _SIGS = {
     "lbm_work_buffer": (_vp, [_vp]),
     "lbm_set_beta": (_c.c_int, [_vp, _c.c_double]),
     "lbm_set_tile": (_c.c_int, [_vp, _c.c_int32, _c.c_int32, _c.c_int32]),
+    "lbm_get_tile": (_c.c_int, [_vp, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "lbm_set_fusion": (_c.c_int, [_vp, _c.c_int32, _c.c_int32]),
     "lbm_spectra": (_c.c_int, [_vp, _c.c_int32, _vp, _vp]),
     "lbm_get_fusion": (_c.c_int, [_vp, _c.POINTER(_c.c_int32)]),

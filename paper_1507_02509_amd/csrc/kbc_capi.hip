@@ -460,6 +460,14 @@ int lbm_set_tile(lbm_ctx* c, int32_t width, int32_t rows_per_thread, int32_t fla
     return LBM_OK;
 }
 
+int lbm_get_tile(const lbm_ctx* c, int32_t* width, int32_t* rows_per_thread, int32_t* flags) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (width) *width = c->shape.width;
+    if (rows_per_thread) *rows_per_thread = c->shape.rpt;
+    if (flags) *flags = c->shape.nt ? LBM_TILE_NONTEMPORAL : 0;
+    return LBM_OK;
+}
+
 int lbm_set_beta(lbm_ctx* c, double beta) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!(beta > 0.0 && beta <= 1.0)) return fail(LBM_EINVAL, "beta must be in (0, 1]");

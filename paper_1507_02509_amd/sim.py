@@ -156,6 +156,14 @@ class Sim:
         L.check(self.lib.lbm_set_tile(self.ctx, int(width), int(rows_per_thread), 1 if nontemporal else 0),
                 "lbm_set_tile")
 
+    @property
+    def tile(self) -> tuple[int, int, bool]:
+        """(width, rows_per_thread, nontemporal) of the step kernel's tile,
+        the flag also being the store kind of the fused launch."""
+        w, r, f = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        L.check(self.lib.lbm_get_tile(self.ctx, ctypes.byref(w), ctypes.byref(r), ctypes.byref(f)), "lbm_get_tile")
+        return int(w.value), int(r.value), bool(f.value & 1)
+
     def set_beta(self, beta: float):
         self.params.beta = float(beta)
         if self.ctx:

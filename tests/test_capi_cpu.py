@@ -98,6 +98,7 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.lbm_set_populations(None, None) == L.LBM_EINVAL
     assert lib.lbm_diagnostics(None, None) == L.LBM_EINVAL
     assert lib.lbm_set_tile(None, 256, 1, 0) == L.LBM_EINVAL
+    assert lib.lbm_get_tile(None, None, None, None) == L.LBM_EINVAL
     assert lib.lbm_set_graph(None, 8) == L.LBM_EINVAL
     assert lib.lbm_set_halo(None, None, None) == L.LBM_EINVAL
     assert lib.lbm_get_edge_rows(None, None, None) == L.LBM_EINVAL

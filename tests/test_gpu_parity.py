@@ -329,6 +329,17 @@ def test_store_kind_bitwise(form, n):
         assert torch.equal(o, outs[0])
 
 
+@pytest.mark.parametrize("form,n,nontemporal", [("f32", 640, True), ("f32", 1024, False), ("f32", 1792, False),
+                                                ("f32", 2048, True), ("f64", 512, True), ("f64", 1024, False),
+                                                ("f16", 1024, True), ("f16", 2048, False), ("f16", 4096, True)])
+def test_default_store_kind(form, n, nontemporal):
+    """The default store kind follows the footprint of the two state buffers:
+    plain stores from 40 MB (FP16 80 MB) to 256 MiB, non-temporal otherwise."""
+    s = Sim(n, n, beta_from_nu(1e-4), form=form)
+    s.init(np.zeros((n, n)), np.zeros((n, n)), mode="eq")
+    assert s.tile[2] == nontemporal
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_diagnostics_parity(orc, form):
     nx, ny = 67, 45
